@@ -1,0 +1,218 @@
+/*
+ * lqs.h -- C ABI of the MI355X staggered-fermion solver library (liblqs.so).
+ *
+ * The library applies the staggered Dirac operator of eq. (1) of Kumar,
+ * Borsanyi, Guenther, Wong, "Portable Lattice QCD implementation based on
+ * OpenCL" (LATTICE2024, Sec. 4.2) and inverts the even-odd normal operator
+ * M = m^2 - D_eo D_oe by conjugate gradient (the "inversion of the Dirac
+ * operator" that Sec. 1 and Sec. 4.2 benchmark), in FP64, FP32 and
+ * FP16-storage arithmetic, for several right-hand sides or several lattices at
+ * once, and provides the link derivative of phi^dag M^-1 phi (a "derivative"
+ * the code design of Sec. 3 places in every backend).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions (the paper leaves these open; fixed here once for every call)
+ *   Extents dims = {Nx, Ny, Nz, Nt}, all even and >= 2, V = Nx Ny Nz Nt,
+ *   Vh = V / 2, V <= 2^30.  Direction mu = 0, 1, 2, 3 is x, y, z, t.
+ *   Lexicographic site index lex = x + Nx (y + Ny (z + Nz t)).
+ *   A site is even when x + y + z + t is even.  Within one parity the site
+ *   with lexicographic index lex has checkerboard index cb = lex >> 1.
+ *   Staggered phases eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y),
+ *   eta_3 = (-1)^(x+y+z); boundaries periodic in x, y, z and antiperiodic in
+ *   t, the sign being carried by the phase of the t-links that leave t = Nt-1.
+ *   Eq. (1) is used as printed (no factor 1/2):
+ *     (D phi)_x = sum_mu [ eps_mu(x) U_{x,mu} phi_{x+mu}
+ *                          - eps_mu(x-mu) U^dag_{x-mu,mu} phi_{x-mu} ]
+ *   with eps_mu the phase of the link including the boundary sign.
+ *
+ * Memory and ownership
+ *   Every field or link pointer is a DEVICE pointer owned by the caller; the
+ *   library never frees it and keeps none past the call.  The library owns
+ *   lqs_ctx (device, stream-independent workspace, tuning cache) and
+ *   lqs_gauge (packed copies of one gauge field); the caller destroys both.
+ *   Device pointers must be 16-byte aligned.
+ *
+ * Complex canonical layouts (interleaved re, im doubles):
+ *   links      [4][Nt][Nz][Ny][Nx][3][3]   row-major 3x3 per link
+ *   lex field  [nrhs][Nt][Nz][Ny][Nx][3]
+ *
+ * Native single-parity colour-vector layouts (lqs_field.data), per right-hand
+ * side r, consecutive right-hand sides one after another:
+ *   LQS_F64  double2 [3][Vh]        element (c, cb) = colour c of site cb
+ *   LQS_F32  float4  [Vh]           colours 0 and 1 of site cb
+ *            float2  [Vh]           colour 2 of site cb      (24 Vh bytes)
+ *   LQS_F16  16-byte word [Vh]      six binary16 (re0 im0 re1 im1 re2 im2)
+ *                                   then one float scale s; value = half * s;
+ *                                   s = max |component| of the site (16 Vh bytes)
+ *
+ * Errors and synchrony
+ *   Every call returns an lqs_status; no C++ exception crosses the ABI.
+ *   Arguments are validated before anything is launched.  A HIP failure
+ *   returns LQS_EHIP with the HIP message in lqs_last_error() (thread-local).
+ *   dslash_apply, dslash_dagger, fermion_force and the field conversions are
+ *   asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ *   cg_solve returns after the solve has finished.
+ *   Calls that share an lqs_ctx must not run concurrently from several host
+ *   threads (the context's workspace is not locked).
+ * ---------------------------------------------------------------------------
+ */
+#ifndef LQS_H
+#define LQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lqs_status;
+enum {
+    LQS_OK = 0,
+    LQS_ENOTCONV = 1,      /* warning: max_iter reached, x holds the last iterate   */
+    LQS_EINVAL = -1,       /* invalid argument (nothing launched)                   */
+    LQS_EHIP = -2,         /* HIP runtime error, see lqs_last_error()               */
+    LQS_ENOMEM = -3,       /* device allocation failed                              */
+    LQS_EBREAKDOWN = -4,   /* CG breakdown: p.Mp <= 0                                */
+    LQS_ENONFINITE = -5,   /* NaN or Inf met in a CG scalar                          */
+    LQS_EUNSUPPORTED = -6  /* format or option not available on this gauge/context */
+};
+
+typedef enum { LQS_F64 = 0, LQS_F32 = 1, LQS_F16 = 2 } lqs_prec;
+
+/* Link storage formats of a gauge object: precision x (18 reals | 12 reals,
+ * third row rebuilt on the fly as conj(row0 x row1), Sec. 4.3). */
+#define LQS_FMT(prec, recon) (1u << (2 * (unsigned)(prec) + ((recon) == 12 ? 1u : 0u)))
+#define LQS_FMT_ALL 0x3Fu
+
+typedef struct lqs_ctx lqs_ctx;
+typedef struct lqs_gauge lqs_gauge;
+
+/* One single-parity colour-vector field of nrhs right-hand sides (non-owning view). */
+typedef struct {
+    void *data;       /* device pointer, native layout of `prec` (above)       */
+    int32_t prec;     /* lqs_prec                                             */
+    int32_t parity;   /* 0 even, 1 odd                                        */
+    int32_t nrhs;     /* 1 .. 16                                              */
+} lqs_field;
+
+/* ---- context and gauge ------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  tune_cache_path: JSON file that
+ * stores autotuned launch parameters across runs (NULL: tune in memory only).
+ * Returns LQS_EINVAL on a bad device, LQS_EHIP on a runtime failure. */
+lqs_status lqs_ctx_create(int32_t device, const char *tune_cache_path, lqs_ctx **out);
+void lqs_ctx_destroy(lqs_ctx *ctx);
+
+/* Autotuning of launch shapes: 1 = sweep on first use of a (kernel, lattice,
+ * format) key and cache the fastest, 0 = use built-in defaults (default). */
+lqs_status lqs_set_tuning(lqs_ctx *ctx, int32_t enable);
+
+/* Pack a canonical link field into the formats of the `formats` bitmask
+ * (LQS_FMT(LQS_F64, 18) is always added).  `links` is read on `stream`; the
+ * call returns once packing has been enqueued.  Links must be SU(3) for the
+ * 12-real formats to reproduce them.  Fails with LQS_EINVAL on odd extents. */
+lqs_status lqs_gauge_create(lqs_ctx *ctx, const int32_t dims[4], const double *links, uint32_t formats,
+                            void *stream, lqs_gauge **out);
+void lqs_gauge_destroy(lqs_gauge *g);
+
+/* Bytes of one native field of nrhs right-hand sides. */
+lqs_status lqs_field_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs, size_t *bytes);
+
+/* lex (canonical, nrhs blocks of V sites) -> native field of out->parity.
+ * Only sites of that parity are read. */
+lqs_status lqs_field_pack(lqs_ctx *ctx, const int32_t dims[4], const double *lex, const lqs_field *out,
+                          void *stream);
+/* native field -> lex; writes only the sites of in->parity, others untouched. */
+lqs_status lqs_field_unpack(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double *lex,
+                            void *stream);
+
+/* ---- the operator ------------------------------------------------------ */
+
+/* out = D_{p,1-p} in: eq. (1) evaluated at the sites of parity p = out->parity,
+ * whose neighbours all have parity 1-p = in->parity.  in and out must have
+ * the same precision and nrhs, opposite parities, and must not overlap.
+ * recon selects the link format (18 or 12) at the fields' precision; the
+ * gauge must hold it (else LQS_EUNSUPPORTED).  nrhs > 1 reads each link once
+ * for all right-hand sides (the multi-vector Dslash of Sec. 4.3). */
+lqs_status dslash_apply(lqs_ctx *ctx, const lqs_gauge *g, int32_t recon, const lqs_field *in, lqs_field *out,
+                        void *stream);
+
+/* out = (D^dag)_{p,1-p} in, the adjoint hop, same arguments as dslash_apply.
+ * (With the phases above D is anti-Hermitian, so this equals -D_{p,1-p}.) */
+lqs_status dslash_dagger(lqs_ctx *ctx, const lqs_gauge *g, int32_t recon, const lqs_field *in, lqs_field *out,
+                         void *stream);
+
+/* ---- the solver -------------------------------------------------------- */
+
+/* One even-parity system M x = b, M = m^2 - D_eo D_oe, with nrhs right-hand
+ * sides sharing the links.  b and x are FP64 native even fields (double2
+ * [nrhs][3][Vh]); x is the initial guess when use_x0 is set, else it is
+ * overwritten from zero. */
+typedef struct {
+    const lqs_gauge *gauge;
+    double mass;
+    int32_t nrhs;
+    const double *b;
+    double *x;
+} lqs_problem;
+
+typedef struct {
+    double tol;                /* stop when ||b - M x|| / ||b|| <= tol (FP64 residual)     */
+    int32_t max_iter;          /* cap on iterations per right-hand side                    */
+    int32_t inner_prec;        /* LQS_F64: plain FP64 CG; LQS_F32/LQS_F16: mixed precision */
+    int32_t inner_recon;       /* 18 or 12: link format of the inner operator              */
+    int32_t reliable_interval; /* mixed: FP64 residual update every K iterations (0: 100)   */
+    double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r|| (0: 0.1)      */
+    int32_t use_x0;            /* 1: start from x                                           */
+    int32_t persistent;        /* 1: all problems in one cooperative launch (nrhs == 1)    */
+} lqs_cg_params;
+
+typedef struct {
+    int32_t status;            /* lqs_status of this right-hand side                        */
+    int32_t iters;             /* inner CG iterations                                       */
+    int32_t reliable_updates;  /* FP64 residual recomputations (incl. the final check)     */
+    int32_t restarts;          /* FP64 CG: restarts after a failed true-residual check      */
+    double true_rel_residual;  /* ||b - M x|| / ||b|| in FP64 at return                     */
+    double seconds;            /* wall time of the whole call                               */
+} lqs_cg_stats;
+
+/* Solve nprob systems.  stats receives one entry per (problem, right-hand
+ * side), in order.  Returns the worst status.  The solve runs on `stream`
+ * and the call returns when it has finished.  persistent = 1 requires
+ * nrhs == 1 for every problem and a context whose device supports
+ * cooperative launches (else LQS_EUNSUPPORTED). */
+lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const lqs_cg_params *params,
+                    lqs_cg_stats *stats, void *stream);
+
+/* ---- the derivative ---------------------------------------------------- */
+
+/* Link derivative of a real function L of chi = M^-1 phi, given X = chi and
+ * Y = M^-1 g with g = 2 dL/dchi^* (Y = NULL means Y = X, i.e. L = phi^dag chi).
+ * With psi_X = D_oe X, psi_Y = D_oe Y and eps_mu the link phase:
+ *   y even: Pi_{y,mu} = eps_mu(y) [psi_X(y+mu) Y(y)^dag + psi_Y(y+mu) X(y)^dag]
+ *   y odd : Pi_{y,mu} = -eps_mu(y) [Y(y+mu) psi_X(y)^dag + X(y+mu) psi_Y(y)^dag]
+ * so that dL = Re sum tr(dU Pi).  mode 0 writes F = coeff * (-TA(U Pi)),
+ * TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6, the su(3) force with
+ * dL/dw = Re tr(F^dag A) for U -> exp(w A) U; mode 1 writes coeff * Pi^dag,
+ * the gradient with respect to the real and imaginary parts of each link
+ * entry.  X, Y: FP64 native even fields (nrhs 1); force: canonical link layout. */
+lqs_status fermion_force(lqs_ctx *ctx, const lqs_gauge *g, const double *X, const double *Y, double coeff,
+                         int32_t mode, double *force, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+const char *lqs_strerror(lqs_status s);
+const char *lqs_last_error(void);
+
+/* Average duration in milliseconds of the hop kernels launched while
+ * profiling was enabled, measured with HIP events on the launch stream.
+ * lqs_profile_hops(ctx, 1) clears and starts, lqs_profile_hops(ctx, 0) stops. */
+lqs_status lqs_profile_hops(lqs_ctx *ctx, int32_t enable);
+lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, int64_t *launches,
+                                   double *avg_ms, int64_t *sites_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQS_H */

@@ -1,0 +1,633 @@
+// cg.hip -- conjugate gradient on the even-odd normal operator
+// M = m^2 - D_eo D_oe (the inversion of Sec. 4.2), in FP64 or with a
+// low-precision inner iteration and FP64 residual updates.
+//
+// Per iteration four kernels run back to back on one stream:
+//   1. t = D_oe p                                      (hop)
+//   2. q = m^2 p - D_eo t and <p,q>                     (hop + fused dot)
+//   3. x += alpha p, r -= alpha q and |r|^2             (fused update + norm)
+//   4. p = r + beta p
+// The dot products are reduced in two fixed-order stages (wave shuffles and
+// LDS inside a block, then the last block to finish sums the block partials)
+// and alpha, beta stay on the device; the host only polls the state record.
+// Every few iterations a gated FP64 group runs between kernels 3 and 4:
+//   x += x_lo, x_lo = 0                                 (mixed precision)
+//   t64 = D_oe x, r_hi = b - (m^2 x - D_eo t64), |r_hi|^2, r = r_hi
+// It does nothing unless the state asks for it: after the iterated residual
+// met the target (then it decides convergence on the FP64 residual), at the
+// iteration cap, or in mixed precision every K iterations or when |r| fell
+// below delta * max|r| (the reliable update of the mixed-precision solvers the
+// paper cites, Clark et al. 2010).
+#include <chrono>
+#include <cmath>
+
+#include "hop.hpp"
+
+namespace lqs {
+
+static constexpr int BLAS_BLOCK = 256;
+static constexpr int MIN_HOP_BLOCK = 64;
+
+// ---------------------------------------------------------------------------
+// scalar bookkeeping, run by one thread of the last block of a reduction
+
+__device__ void fin_alpha(CgState &S, double pq)
+{
+    if (!isfinite(pq)) S.phase = CG_NONFINITE;
+    else if (!(pq > 0.0)) S.phase = CG_BREAKDOWN;
+    else S.alpha = S.rho / pq;
+}
+
+__device__ void fin_update(CgState &S, double r2)
+{
+    S.rho_old = S.rho;
+    S.rho = r2;
+    S.beta = r2 / S.rho_old;
+    S.iters += 1;
+    S.since_rel += 1;
+    if (!isfinite(r2)) {
+        S.phase = CG_NONFINITE;
+        return;
+    }
+    if (r2 > S.max_rho) S.max_rho = r2;
+    if (r2 <= S.stop2 || S.iters >= S.max_iter) {
+        S.phase = CG_INNER_DONE;
+        S.reliable_pending = 1;
+        return;
+    }
+    if (S.rel_interval > 0 && (S.since_rel >= S.rel_interval || r2 < S.delta2 * S.max_rho)) S.reliable_pending = 1;
+}
+
+// mode: 0 reliable update inside the iteration, 1 initial residual, 2 measure only
+__device__ void fin_residual(CgState &S, double r2, int mode)
+{
+    S.true_r2 = r2;
+    if (mode == 2) return;
+    if (mode == 1) {
+        S.rho = r2;
+        S.max_rho = r2;
+        S.phase = isfinite(r2) ? (r2 <= S.stop2 ? CG_CONVERGED : CG_RUNNING) : CG_NONFINITE;
+        return;
+    }
+    S.nreliable += 1;
+    S.reliable_pending = 0;
+    S.since_rel = 0;
+    if (!isfinite(r2)) {
+        S.phase = CG_NONFINITE;
+    } else if (r2 <= S.stop2) {
+        S.phase = CG_CONVERGED;
+    } else if (S.iters >= S.max_iter) {
+        S.phase = CG_MAXITER;
+    } else if (S.rel_interval == 0) {
+        // FP64 solver whose iterated residual drifted: restart from r = b - M x
+        S.rho = r2;
+        S.max_rho = r2;
+        S.beta = 0.0;
+        S.restarts += 1;
+        S.phase = CG_RUNNING;
+    } else {
+        // mixed precision: continue with the FP64 residual, keep p
+        S.beta = r2 / S.rho_old;
+        S.rho = r2;
+        S.max_rho = r2;
+        S.phase = CG_RUNNING;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. q = m^2 p - D_eo t, <p, q>  (output parity even; t odd)
+
+template <int P, int R, int K>
+__global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
+                                                         int64_t stride, double m2, CgState *st, double *partials,
+                                                         int max_blocks, int nrhs)
+{
+    typedef typename RealOf<P>::type T;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = cb < g.vh;
+    const int r0 = blockIdx.y * K;
+    bool blk[K], act[K];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        blk[j] = (r0 + j < nrhs) && st[r0 + j].phase == CG_RUNNING;
+        act[j] = blk[j] && valid;
+        any |= blk[j];
+    }
+    if (!any) return;
+    double dot[K];
+    V3<T> acc[K];
+    if (valid) {
+        const Site s = decode(g, cb, 0);
+        hop_site<P, R, K>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        dot[j] = 0.0;
+        if (!act[j]) continue;
+        const V3<T> pv = SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
+        V3<T> qv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            qv.c[a].re = (T)m2 * pv.c[a].re - acc[j].c[a].re;
+            qv.c[a].im = (T)m2 * pv.c[a].im - acc[j].c[a].im;
+            dot[j] += (double)pv.c[a].re * (double)qv.c[a].re + (double)pv.c[a].im * (double)qv.c[a].im;
+        }
+        SpinorIO<P>::store(q + (r0 + j) * stride, g.vh, cb, qv);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!blk[j]) continue;
+        const int r = r0 + j;
+        const double s = block_sum(dot[j]);
+        if (threadIdx.x == 0) partials[(int64_t)r * max_blocks + blockIdx.x] = s;
+        if (last_block(&st[r].counter[CNT_DOT], gridDim.x)) {
+            const double pq = sum_partials(partials + (int64_t)r * max_blocks, gridDim.x);
+            if (threadIdx.x == 0) fin_alpha(st[r], pq);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. x_lo += alpha p, r -= alpha q, |r|^2   (grid-stride, blockIdx.y = rhs)
+
+template <int PA, int PI>
+__global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, char *r, const char *p, const char *q,
+                                                            int64_t sa, int64_t si, CgState *st, double *partials,
+                                                            int max_blocks)
+{
+    typedef typename RealOf<PA>::type T;
+    const int rhs = blockIdx.y;
+    CgState &S = st[rhs];
+    if (S.phase != CG_RUNNING) return;
+    const T alpha = (T)S.alpha;
+    x += rhs * sa;
+    r += rhs * sa;
+    p += rhs * si;
+    q += rhs * si;
+    double local = 0.0;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<T> pv = vcast<T>(SpinorIO<PI>::load(p, vh, cb));
+        const V3<T> qv = vcast<T>(SpinorIO<PI>::load(q, vh, cb));
+        V3<T> xv = SpinorIO<PA>::load(x, vh, cb);
+        V3<T> rv = SpinorIO<PA>::load(r, vh, cb);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xv.c[a].re += alpha * pv.c[a].re;
+            xv.c[a].im += alpha * pv.c[a].im;
+            rv.c[a].re -= alpha * qv.c[a].re;
+            rv.c[a].im -= alpha * qv.c[a].im;
+            local += (double)rv.c[a].re * (double)rv.c[a].re + (double)rv.c[a].im * (double)rv.c[a].im;
+        }
+        SpinorIO<PA>::store(x, vh, cb, xv);
+        SpinorIO<PA>::store(r, vh, cb, rv);
+    }
+    const double s = block_sum(local);
+    if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
+    if (last_block(&S.counter[CNT_UPDATE], gridDim.x)) {
+        const double r2 = sum_partials(partials + (int64_t)rhs * max_blocks, gridDim.x);
+        if (threadIdx.x == 0) fin_update(S, r2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. p = r + beta p
+
+template <int PA, int PI>
+__global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char *r, char *p, int64_t sa, int64_t si,
+                                                             const CgState *st)
+{
+    typedef typename RealOf<PA>::type T;
+    typedef typename RealOf<PI>::type TI;
+    const int rhs = blockIdx.y;
+    const CgState &S = st[rhs];
+    if (S.phase != CG_RUNNING) return;
+    const T beta = (T)S.beta;
+    r += rhs * sa;
+    p += rhs * si;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<T> rv = SpinorIO<PA>::load(r, vh, cb);
+        const V3<T> pv = vcast<T>(SpinorIO<PI>::load(p, vh, cb));
+        V3<T> o;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o.c[a].re = rv.c[a].re + beta * pv.c[a].re;
+            o.c[a].im = rv.c[a].im + beta * pv.c[a].im;
+        }
+        SpinorIO<PI>::store(p, vh, cb, vcast<TI>(o));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 group: x += x_lo, x_lo = 0   (gate: 1 = reliable pending, 0 = always)
+
+template <int PA>
+__global__ void __launch_bounds__(BLAS_BLOCK) accumulate_kernel(int vh, double *x, char *xlo, int64_t sa,
+                                                                const CgState *st, int gated)
+{
+    const int rhs = blockIdx.y;
+    if (gated && !st[rhs].reliable_pending) return;
+    char *xd = (char *)x + rhs * spinor_bytes_per_site(F64) * (int64_t)vh;
+    xlo += rhs * sa;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        V3<double> xv = SpinorIO<F64>::load(xd, vh, cb);
+        const V3<double> lv = vcast<double>(SpinorIO<PA>::load(xlo, vh, cb));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xv.c[a].re += lv.c[a].re;
+            xv.c[a].im += lv.c[a].im;
+        }
+        SpinorIO<F64>::store(xd, vh, cb, xv);
+        SpinorIO<PA>::store(xlo, vh, cb, vcast<typename RealOf<PA>::type>(vzero<double>()));
+    }
+}
+
+// r_hi = b - (m^2 x - D_eo t64) in FP64, |r_hi|^2; r (PA) = r_hi unless mode 2.
+// gate_mode 2: only right-hand sides with a pending update; 0: all.
+template <int R, int PA, int K>
+__global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const char *t64, const char *x,
+                                                       const char *b, char *r, int64_t sa, double m2, CgState *st,
+                                                       double *partials, int max_blocks, int nrhs, int gate_mode,
+                                                       int mode)
+{
+    const int64_t s64 = spinor_bytes_per_site(F64) * (int64_t)g.vh;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = cb < g.vh;
+    const int r0 = blockIdx.y * K;
+    bool blk[K], act[K];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        blk[j] = (r0 + j < nrhs) && (gate_mode == 0 || st[r0 + j].reliable_pending);
+        act[j] = blk[j] && valid;
+        any |= blk[j];
+    }
+    if (!any) return;
+    V3<double> acc[K];
+    double nrm[K];
+    if (valid) {
+        const Site s = decode(g, cb, 0);
+        hop_site<F64, R, K>(g, L, 0, s, cb, t64 + r0 * s64, s64, act, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        nrm[j] = 0.0;
+        if (!act[j]) continue;
+        const V3<double> xv = SpinorIO<F64>::load(x + (r0 + j) * s64, g.vh, cb);
+        const V3<double> bv = SpinorIO<F64>::load(b + (r0 + j) * s64, g.vh, cb);
+        V3<double> rv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            rv.c[a].re = bv.c[a].re - (m2 * xv.c[a].re - acc[j].c[a].re);
+            rv.c[a].im = bv.c[a].im - (m2 * xv.c[a].im - acc[j].c[a].im);
+            nrm[j] += rv.c[a].re * rv.c[a].re + rv.c[a].im * rv.c[a].im;
+        }
+        if (mode != 2) SpinorIO<PA>::store(r + (r0 + j) * sa, g.vh, cb, vcast<typename RealOf<PA>::type>(rv));
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!blk[j]) continue;
+        const int rr = r0 + j;
+        const double s = block_sum(nrm[j]);
+        if (threadIdx.x == 0) partials[(int64_t)rr * max_blocks + blockIdx.x] = s;
+        if (last_block(&st[rr].counter[CNT_RESID], gridDim.x)) {
+            const double r2 = sum_partials(partials + (int64_t)rr * max_blocks, gridDim.x);
+            if (threadIdx.x == 0) fin_residual(st[rr], r2, mode);
+        }
+    }
+}
+
+// |b|^2 per right-hand side; cold start: x = 0, r = b, p = b, x_lo = 0.
+template <int PA, int PI>
+__global__ void __launch_bounds__(BLAS_BLOCK) init_kernel(int vh, const char *b, double *x, char *r, char *p,
+                                                          char *xlo, int64_t sa, int64_t si, CgState *st,
+                                                          double *partials, int max_blocks, int cold)
+{
+    typedef typename RealOf<PA>::type T;
+    typedef typename RealOf<PI>::type TI;
+    const int rhs = blockIdx.y;
+    const int64_t s64 = spinor_bytes_per_site(F64) * (int64_t)vh;
+    b += rhs * s64;
+    char *xd = (char *)x + rhs * s64;
+    double local = 0.0;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<double> bv = SpinorIO<F64>::load(b, vh, cb);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) local += bv.c[a].re * bv.c[a].re + bv.c[a].im * bv.c[a].im;
+        if (cold) {
+            SpinorIO<F64>::store(xd, vh, cb, vzero<double>());
+            SpinorIO<PA>::store(r + rhs * sa, vh, cb, vcast<T>(bv));
+            SpinorIO<PI>::store(p + rhs * si, vh, cb, vcast<TI>(bv));
+        }
+        if (xlo) SpinorIO<PA>::store(xlo + rhs * sa, vh, cb, vzero<T>());
+    }
+    const double s = block_sum(local);
+    if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
+    if (last_block(&st[rhs].counter[CNT_MISC], gridDim.x)) {
+        const double b2 = sum_partials(partials + (int64_t)rhs * max_blocks, gridDim.x);
+        if (threadIdx.x == 0) {
+            CgState &S = st[rhs];
+            S.b2 = b2;
+            S.stop2 = S.stop2 * b2;  // the host stored tol^2 here
+            if (cold) {
+                S.rho = b2;
+                S.max_rho = b2;
+                S.true_r2 = b2;
+                S.phase = (b2 == 0.0) ? CG_CONVERGED : (isfinite(b2) ? CG_RUNNING : CG_NONFINITE);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int blas_blocks(int64_t vh)
+{
+    int64_t b = (vh + BLAS_BLOCK - 1) / BLAS_BLOCK;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+int cg_partials_needed(const Gauge &gauge, int nrhs)
+{
+    (void)nrhs;
+    int64_t hop_blocks = (gauge.vh + MIN_HOP_BLOCK - 1) / MIN_HOP_BLOCK;
+    return (int)(hop_blocks > 1024 ? hop_blocks : 1024);
+}
+
+template <int P, int R>
+static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShape sh, hipStream_t s)
+{
+    const Geom &g = gauge.g;
+    const int64_t stride = field_bytes(g, P, 1);
+    const LinkRef L = gauge.ref(P, R);
+    dim3 grid((g.vh + sh.block - 1) / sh.block, (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread);
+    const double m2 = v.mass * v.mass;
+#define LQS_ND(K)                                                                                                 \
+    hipLaunchKernelGGL((normal_dot_kernel<P, R, K>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,         \
+                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs)
+    if (sh.rhs_per_thread == 1) LQS_ND(1);
+    else if (sh.rhs_per_thread == 2) LQS_ND(2);
+    else LQS_ND(4);
+#undef LQS_ND
+    LQS_HIP(hipGetLastError());
+}
+
+void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape shd, hipStream_t s)
+{
+    if (v.prec == F64 && v.recon == 18) launch_normal_dot<F64, 18>(gauge, v, shd, s);
+    else if (v.prec == F64) launch_normal_dot<F64, 12>(gauge, v, shd, s);
+    else if (v.prec == F32 && v.recon == 18) launch_normal_dot<F32, 18>(gauge, v, shd, s);
+    else if (v.prec == F32) launch_normal_dot<F32, 12>(gauge, v, shd, s);
+    else if (v.recon == 18) launch_normal_dot<F16, 18>(gauge, v, shd, s);
+    else launch_normal_dot<F16, 12>(gauge, v, shd, s);
+}
+
+template <int PA, int PI> static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, hipStream_t s)
+{
+    const int vh = (int)gauge.vh;
+    const int64_t sa = field_bytes(gauge.g, PA, 1), si = field_bytes(gauge.g, PI, 1);
+    dim3 grid(blas_blocks(vh), v.nrhs);
+    if (which == 0)
+        hipLaunchKernelGGL((update_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.xlo, (char *)v.r,
+                           (const char *)v.p, (const char *)v.q, sa, si, v.state, v.partials, v.max_blocks);
+    else
+        hipLaunchKernelGGL((pupdate_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (const char *)v.r,
+                           (char *)v.p, sa, si, (const CgState *)v.state);
+    LQS_HIP(hipGetLastError());
+}
+
+template <int PA>
+static void launch_residual_t(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+{
+    const Geom &g = gauge.g;
+    const int block = 256;
+    const int K = v.nrhs >= 2 ? 2 : 1;
+    dim3 grid((g.vh + block - 1) / block, (v.nrhs + K - 1) / K);
+    const LinkRef L = gauge.ref(F64, 18);
+    const int64_t sa = field_bytes(g, PA, 1);
+    char *r = (char *)(mode == 2 ? nullptr : v.r);
+    const double m2 = v.mass * v.mass;
+    if (K == 1)
+        hipLaunchKernelGGL((residual_kernel<18, PA, 1>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,
+                           (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
+                           gate_mode, mode);
+    else
+        hipLaunchKernelGGL((residual_kernel<18, PA, 2>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,
+                           (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
+                           gate_mode, mode);
+    LQS_HIP(hipGetLastError());
+}
+
+static void launch_residual(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+{
+    if (v.acc_prec == F64) launch_residual_t<F64>(gauge, v, gate_mode, mode, s);
+    else launch_residual_t<F32>(gauge, v, gate_mode, mode, s);
+}
+
+static void launch_accumulate(const Gauge &gauge, const CgVectors &v, int gated, hipStream_t s)
+{
+    const int vh = (int)gauge.vh;
+    dim3 grid(blas_blocks(vh), v.nrhs);
+    const int64_t sa = field_bytes(gauge.g, v.acc_prec, 1);
+    LQS_REQUIRE(v.acc_prec == F32, LQS_EUNSUPPORTED, "accumulate needs an FP32 inner solution");
+    hipLaunchKernelGGL((accumulate_kernel<F32>), grid, dim3(BLAS_BLOCK), 0, s, vh, v.x, (char *)v.xlo, sa,
+                       (const CgState *)v.state, gated);
+    LQS_HIP(hipGetLastError());
+}
+
+// The FP64 residual group: x += x_lo (mixed), t64 = D_oe x, residual kernel.
+static void residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+{
+    (void)ctx;
+    if (v.acc_prec != F64 && mode == 0) launch_accumulate(gauge, v, gate_mode == 2 ? 1 : 0, s);
+    LaunchShape sh = default_hop_shape(F64, v.nrhs);
+    launch_hop_gated(gauge.g, gauge.ref(F64, 18), F64, 18, 0, 1, v.nrhs, v.x, v.t64, v.state, gate_mode, sh, s);
+    launch_residual(gauge, v, gate_mode, mode, s);
+}
+
+void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_t s)
+{
+    const int vh = (int)gauge.vh;
+    dim3 grid(blas_blocks(vh), v.nrhs);
+    const int64_t sa = field_bytes(gauge.g, v.acc_prec, 1), si = field_bytes(gauge.g, v.prec, 1);
+    char *xlo = v.acc_prec == F64 ? nullptr : (char *)v.xlo;
+    const int cold = use_x0 ? 0 : 1;
+#define LQS_INIT(PA, PI)                                                                                          \
+    hipLaunchKernelGGL((init_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (const char *)v.b, v.x,           \
+                       (char *)v.r, (char *)v.p, xlo, sa, si, v.state, v.partials, v.max_blocks, cold)
+    if (v.acc_prec == F64) LQS_INIT(F64, F64);
+    else if (v.prec == F32) LQS_INIT(F32, F32);
+    else LQS_INIT(F32, F16);
+#undef LQS_INIT
+    LQS_HIP(hipGetLastError());
+    if (use_x0) {
+        residual_group(ctx, gauge, v, 0, 1, s);
+        launch_convert(gauge.g, v.nrhs, v.acc_prec, v.r, v.prec, v.p, s);
+    }
+}
+
+void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, bool with_reliable)
+{
+    LaunchShape sh = default_hop_shape(v.prec, v.nrhs);
+    LaunchShape shd = sh;
+    if (ctx.tuner) {
+        LaunchShape t;
+        if (ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, v.prec, v.recon, v.nrhs), t)) sh = t;
+        if (ctx.tuner->lookup(tune_key(ctx, "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), t)) shd = t;
+    }
+    // 1. t = D_oe p
+    prof_begin(ctx, s);
+    launch_hop_gated(gauge.g, gauge.ref(v.prec, v.recon), v.prec, v.recon, 0, 1, v.nrhs, v.p, v.t, v.state, 1, sh, s);
+    prof_end(ctx, v.prec, v.recon, gauge.vh * v.nrhs, s);
+    // 2. q = m^2 p - D_eo t, <p,q>
+    launch_normal_dot_shape(gauge, v, shd, s);
+    // 3. update
+    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 0, s);
+    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, s);
+    else launch_blas<F32, F16>(gauge, v, 0, s);
+    // FP64 residual group (gated)
+    if (with_reliable) residual_group(ctx, gauge, v, 2, 0, s);
+    // 4. p = r + beta p
+    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 1, s);
+    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 1, s);
+    else launch_blas<F32, F16>(gauge, v, 1, s);
+}
+
+// ---------------------------------------------------------------------------
+// one problem (nrhs >= 1) with the multi-kernel iteration
+
+static bool final_phase(int32_t ph)
+{
+    return ph == CG_CONVERGED || ph == CG_BREAKDOWN || ph == CG_NONFINITE || ph == CG_MAXITER;
+}
+
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const Gauge &gauge = *pb.gauge;
+    const Geom &g = gauge.g;
+    const int nrhs = pb.nrhs;
+    const bool mixed = prm.inner_prec != F64;
+    CgVectors v{};
+    v.prec = prm.inner_prec;
+    v.acc_prec = mixed ? F32 : F64;
+    v.recon = prm.inner_recon == 12 ? 12 : 18;
+    v.nrhs = nrhs;
+    v.mass = pb.mass;
+    (void)gauge.ref(v.prec, v.recon);  // format must exist
+    const int64_t fp = field_bytes(g, v.prec, nrhs), fa = field_bytes(g, v.acc_prec, nrhs),
+                  f64 = field_bytes(g, F64, nrhs);
+    v.p = ctx.workspace("cg.p", fp);
+    v.q = ctx.workspace("cg.q", fp);
+    v.t = ctx.workspace("cg.t", fp);
+    v.x = pb.x;
+    v.b = (double *)pb.b;
+    if (mixed) {
+        v.r = ctx.workspace("cg.r", fa);
+        v.xlo = ctx.workspace("cg.xlo", fa);
+        v.t64 = ctx.workspace("cg.t64", f64);
+        v.rhi = nullptr;
+    } else {
+        v.r = ctx.workspace("cg.r", f64);
+        v.xlo = pb.x;
+        v.t64 = v.t;
+        v.rhi = (double *)v.r;
+    }
+    v.max_blocks = cg_partials_needed(gauge, nrhs);
+    v.partials = (double *)ctx.workspace("cg.partials", sizeof(double) * (size_t)v.max_blocks * nrhs);
+    v.state = (CgState *)ctx.workspace("cg.state", sizeof(CgState) * nrhs);
+
+    // initial state records
+    const size_t sbytes = sizeof(CgState) * nrhs;
+    if (ctx.host_state_bytes < 2 * sbytes) {
+        if (ctx.host_state) LQS_HIP(hipHostFree(ctx.host_state));
+        ctx.host_state = nullptr;
+        LQS_HIP(hipHostMalloc(&ctx.host_state, 2 * sbytes, hipHostMallocDefault));
+        ctx.host_state_bytes = 2 * sbytes;
+    }
+    CgState *hs[2] = {(CgState *)ctx.host_state, (CgState *)((char *)ctx.host_state + sbytes)};
+    const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
+    const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.1) : 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        CgState S{};
+        S.stop2 = prm.tol * prm.tol;
+        S.delta2 = delta * delta;
+        S.rel_interval = rel_interval;
+        S.max_iter = prm.max_iter;
+        S.phase = CG_RUNNING;
+        hs[0][r] = S;
+    }
+    LQS_HIP(hipMemcpyAsync(v.state, hs[0], sbytes, hipMemcpyHostToDevice, s));
+    cg_init(ctx, gauge, v, prm.use_x0 != 0, s);
+
+    // iterate in chunks; the FP64 group closes each chunk; poll the state
+    const int chunk = 4;
+    const int poll_every = 2;  // chunks between polls
+    hipEvent_t ev[2];
+    LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    LQS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    int inflight = 0, slot = 0;
+    int64_t enqueued = 0;
+    const int64_t cap = (int64_t)prm.max_iter + 16 * chunk + 64;
+    bool done = false;
+    try {
+        while (!done) {
+            for (int c = 0; c < poll_every; ++c) {
+                for (int i = 0; i < chunk; ++i) cg_iteration(ctx, gauge, v, s, i == chunk - 1);
+                enqueued += chunk;
+            }
+            LQS_HIP(hipMemcpyAsync(hs[slot], v.state, sbytes, hipMemcpyDeviceToHost, s));
+            LQS_HIP(hipEventRecord(ev[slot], s));
+            ++inflight;
+            slot ^= 1;
+            if (inflight == 2) {
+                // wait for the older poll
+                LQS_HIP(hipEventSynchronize(ev[slot]));
+                --inflight;
+                bool all = true;
+                for (int r = 0; r < nrhs; ++r) all &= final_phase(hs[slot][r].phase);
+                if (all || enqueued > cap) done = true;
+            }
+        }
+        LQS_HIP(hipEventSynchronize(ev[slot ^ 1]));
+        LQS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        throw;
+    }
+    LQS_HIP(hipEventDestroy(ev[0]));
+    LQS_HIP(hipEventDestroy(ev[1]));
+
+    // right-hand sides that stopped without an FP64 check (breakdown,
+    // non-finite, host cap) get x += x_lo and a measured residual
+    LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
+    LQS_HIP(hipStreamSynchronize(s));
+    bool need = false;
+    for (int r = 0; r < nrhs; ++r) need |= !(hs[0][r].phase == CG_CONVERGED || hs[0][r].phase == CG_MAXITER);
+    if (need) {
+        if (mixed) launch_accumulate(gauge, v, 0, s);
+        residual_group(ctx, gauge, v, 0, 2, s);
+        LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipStreamSynchronize(s));
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nrhs; ++r) {
+        const CgState &S = hs[0][r];
+        lqs_cg_stats &o = stats[r];
+        o.iters = S.iters;
+        o.reliable_updates = S.nreliable;
+        o.restarts = S.restarts;
+        o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
+        o.seconds = secs;
+        switch (S.phase) {
+        case CG_CONVERGED: o.status = LQS_OK; break;
+        case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;
+        case CG_NONFINITE: o.status = LQS_ENONFINITE; break;
+        default: o.status = LQS_ENOTCONV; break;
+        }
+    }
+}
+
+}  // namespace lqs

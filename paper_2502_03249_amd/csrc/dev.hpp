@@ -1,0 +1,474 @@
+// dev.hpp -- device-side building blocks of the staggered operator on gfx950:
+// complex and SU(3) arithmetic, the native storage formats of links and
+// colour vectors, and the checkerboard geometry with the staggered phases.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lqs {
+
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2 };
+
+typedef _Float16 half_t;
+
+// ---------------------------------------------------------------------------
+// complex numbers, colour vectors, SU(3) matrices
+
+template <typename T> struct Cx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ Cx<T> cjmul(Cx<T> a, Cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+template <typename T> struct V3 {
+    Cx<T> c[3];
+};
+
+template <typename T> struct M3 {
+    Cx<T> e[3][3];
+};
+
+template <typename T> __device__ __forceinline__ V3<T> vzero()
+{
+    V3<T> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v.c[a] = {T(0), T(0)};
+    return v;
+}
+
+// U v
+template <typename T> __device__ __forceinline__ V3<T> mv(const M3<T> &u, const V3<T> &v)
+{
+    V3<T> w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Cx<T> s = cmul(u.e[a][0], v.c[0]);
+        s = cadd(s, cmul(u.e[a][1], v.c[1]));
+        s = cadd(s, cmul(u.e[a][2], v.c[2]));
+        w.c[a] = s;
+    }
+    return w;
+}
+
+// U^dag v
+template <typename T> __device__ __forceinline__ V3<T> mdv(const M3<T> &u, const V3<T> &v)
+{
+    V3<T> w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Cx<T> s = cjmul(u.e[0][a], v.c[0]);
+        s = cadd(s, cjmul(u.e[1][a], v.c[1]));
+        s = cadd(s, cjmul(u.e[2][a], v.c[2]));
+        w.c[a] = s;
+    }
+    return w;
+}
+
+// acc += w or acc -= w
+template <typename T> __device__ __forceinline__ void accum(V3<T> &acc, const V3<T> &w, bool negate)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T re = negate ? -w.c[a].re : w.c[a].re;
+        T im = negate ? -w.c[a].im : w.c[a].im;
+        acc.c[a].re += re;
+        acc.c[a].im += im;
+    }
+}
+
+// Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
+template <typename T> __device__ __forceinline__ void rebuild_row2(M3<T> &u)
+{
+    Cx<T> a = csub(cmul(u.e[0][1], u.e[1][2]), cmul(u.e[0][2], u.e[1][1]));
+    Cx<T> b = csub(cmul(u.e[0][2], u.e[1][0]), cmul(u.e[0][0], u.e[1][2]));
+    Cx<T> c = csub(cmul(u.e[0][0], u.e[1][1]), cmul(u.e[0][1], u.e[1][0]));
+    u.e[2][0] = {a.re, -a.im};
+    u.e[2][1] = {b.re, -b.im};
+    u.e[2][2] = {c.re, -c.im};
+}
+
+// ---------------------------------------------------------------------------
+// storage formats
+//
+// Links of one (direction, parity) block are stored as arrays of Vh words, one
+// array after the other ("word-major"), so that a wavefront reading one word
+// of consecutive sites touches one contiguous run of memory:
+//   F64, 18 reals: 9 x double2 (complex element k = 3*row + col)
+//   F64, 12 reals: 6 x double2 (rows 0 and 1)
+//   F32, 18 reals: 4 x float4 (elements 0-1, 2-3, 4-5, 6-7) + 1 x float2 (element 8)
+//   F32, 12 reals: 3 x float4
+//   F16, 18 reals: 2 x 16-byte (elements 0-3, 4-7) + 1 x 4-byte (element 8)
+//   F16, 12 reals: 1 x 16-byte (elements 0-3) + 1 x 8-byte (elements 4-5)
+// The eight blocks follow each other in the order (mu, parity) = 2*mu + parity.
+
+__host__ __device__ constexpr int link_block_bytes_per_site(int prec, int recon)
+{
+    return (prec == F64 ? 16 : prec == F32 ? 8 : 4) * (recon == 12 ? 6 : 9);
+}
+
+template <int P> struct RealOf { typedef float type; };
+template <> struct RealOf<F64> { typedef double type; };
+
+struct alignas(16) W16 { uint32_t w[4]; };
+struct alignas(8) W8 { uint32_t w[2]; };
+
+template <typename To, typename From> __device__ __forceinline__ To bitcast(const From &f)
+{
+    return __builtin_bit_cast(To, f);
+}
+
+template <typename T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
+
+__device__ __forceinline__ void h8_to_cx(const W16 &w, Cx<float> *out)
+{
+    struct H8 { half_t h[8]; } h = bitcast<H8>(w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = {(float)h.h[2 * k], (float)h.h[2 * k + 1]};
+}
+
+__device__ __forceinline__ W16 cx_to_h8(const Cx<float> *in)
+{
+    struct H8 { half_t h[8]; } h;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        h.h[2 * k] = (half_t)in[k].re;
+        h.h[2 * k + 1] = (half_t)in[k].im;
+    }
+    return bitcast<W16>(h);
+}
+
+// Load the link of site cb from a (direction, parity) block; the block base
+// points at word array 0 and vh is the array length.
+template <int P, int R> struct LinkIO;
+
+template <int R> struct LinkIO<F64, R> {
+    __device__ static __forceinline__ M3<double> load(const void *base, int64_t vh, int cb)
+    {
+        const double2 *b = (const double2 *)base;
+        M3<double> u;
+        constexpr int rows = (R == 12) ? 2 : 3;
+#pragma unroll
+        for (int k = 0; k < 3 * rows; ++k) {
+            double2 d = ldg(b + k * vh + cb);
+            u.e[k / 3][k % 3] = {d.x, d.y};
+        }
+        if (R == 12) rebuild_row2(u);
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<double> &u)
+    {
+        double2 *b = (double2 *)base;
+        constexpr int rows = (R == 12) ? 2 : 3;
+#pragma unroll
+        for (int k = 0; k < 3 * rows; ++k) b[k * vh + cb] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
+    }
+};
+
+template <int R> struct LinkIO<F32, R> {
+    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    {
+        const float4 *b = (const float4 *)base;
+        M3<float> u;
+        constexpr int n4 = (R == 12) ? 3 : 4;
+#pragma unroll
+        for (int k = 0; k < n4; ++k) {
+            float4 d = ldg(b + k * vh + cb);
+            u.e[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
+            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
+        }
+        if (R == 12) {
+            rebuild_row2(u);
+        } else {
+            const float2 *t = (const float2 *)(b + 4 * vh);
+            float2 d = ldg(t + cb);
+            u.e[2][2] = {d.x, d.y};
+        }
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<float> &u)
+    {
+        float4 *b = (float4 *)base;
+        constexpr int n4 = (R == 12) ? 3 : 4;
+#pragma unroll
+        for (int k = 0; k < n4; ++k) {
+            Cx<float> a = u.e[(2 * k) / 3][(2 * k) % 3], c = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            b[k * vh + cb] = make_float4(a.re, a.im, c.re, c.im);
+        }
+        if (R != 12) {
+            float2 *t = (float2 *)(b + 4 * vh);
+            t[cb] = make_float2(u.e[2][2].re, u.e[2][2].im);
+        }
+    }
+};
+
+template <int R> struct LinkIO<F16, R> {
+    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    {
+        const W16 *b = (const W16 *)base;
+        M3<float> u;
+        Cx<float> e[9];
+        h8_to_cx(ldg(b + cb), e);
+        if (R == 12) {
+            const W8 *t = (const W8 *)(b + vh);
+            W8 w = ldg(t + cb);
+            struct H4 { half_t h[4]; } h = bitcast<H4>(w);
+            e[4] = {(float)h.h[0], (float)h.h[1]};
+            e[5] = {(float)h.h[2], (float)h.h[3]};
+        } else {
+            h8_to_cx(ldg(b + vh + cb), e + 4);
+            const uint32_t *t = (const uint32_t *)(b + 2 * vh);
+            struct H2 { half_t h[2]; } h = bitcast<H2>(ldg(t + cb));
+            e[8] = {(float)h.h[0], (float)h.h[1]};
+        }
+        constexpr int n = (R == 12) ? 6 : 9;
+#pragma unroll
+        for (int k = 0; k < n; ++k) u.e[k / 3][k % 3] = e[k];
+        if (R == 12) rebuild_row2(u);
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<float> &u)
+    {
+        W16 *b = (W16 *)base;
+        Cx<float> e[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) e[k] = u.e[k / 3][k % 3];
+        b[cb] = cx_to_h8(e);
+        if (R == 12) {
+            struct H4 { half_t h[4]; } h;
+            h.h[0] = (half_t)e[4].re;
+            h.h[1] = (half_t)e[4].im;
+            h.h[2] = (half_t)e[5].re;
+            h.h[3] = (half_t)e[5].im;
+            ((W8 *)(b + vh))[cb] = bitcast<W8>(h);
+        } else {
+            b[vh + cb] = cx_to_h8(e + 4);
+            struct H2 { half_t h[2]; } h;
+            h.h[0] = (half_t)e[8].re;
+            h.h[1] = (half_t)e[8].im;
+            ((uint32_t *)(b + 2 * vh))[cb] = bitcast<uint32_t>(h);
+        }
+    }
+};
+
+// Colour vectors of one parity and one right-hand side (see lqs.h):
+//   F64: double2 [3][Vh]; F32: float4 [Vh] + float2 [Vh]; F16: 16-byte [Vh]
+//   (six binary16 scaled by a float per site).
+__host__ __device__ constexpr int64_t spinor_bytes_per_site(int prec)
+{
+    return prec == F64 ? 48 : prec == F32 ? 24 : 16;
+}
+
+template <int P> struct SpinorIO;
+
+template <> struct SpinorIO<F64> {
+    __device__ static __forceinline__ V3<double> load(const void *base, int64_t vh, int cb)
+    {
+        const double2 *b = (const double2 *)base;
+        V3<double> v;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double2 d = ldg(b + a * vh + cb);
+            v.c[a] = {d.x, d.y};
+        }
+        return v;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<double> &v)
+    {
+        double2 *b = (double2 *)base;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b[a * vh + cb] = make_double2(v.c[a].re, v.c[a].im);
+    }
+};
+
+template <> struct SpinorIO<F32> {
+    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    {
+        const float4 *b = (const float4 *)base;
+        float4 d = ldg(b + cb);
+        float2 e = ldg((const float2 *)(b + vh) + cb);
+        V3<float> v;
+        v.c[0] = {d.x, d.y};
+        v.c[1] = {d.z, d.w};
+        v.c[2] = {e.x, e.y};
+        return v;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<float> &v)
+    {
+        float4 *b = (float4 *)base;
+        b[cb] = make_float4(v.c[0].re, v.c[0].im, v.c[1].re, v.c[1].im);
+        ((float2 *)(b + vh))[cb] = make_float2(v.c[2].re, v.c[2].im);
+    }
+};
+
+struct alignas(16) SpH {
+    half_t h[6];
+    float s;
+};
+
+template <> struct SpinorIO<F16> {
+    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    {
+        (void)vh;
+        W16 w = ldg((const W16 *)base + cb);
+        SpH q = bitcast<SpH>(w);
+        V3<float> v;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v.c[a] = {(float)q.h[2 * a] * q.s, (float)q.h[2 * a + 1] * q.s};
+        return v;
+    }
+    // Scale = max |component| of the site; components stored as binary16 of
+    // value / scale (round to nearest even); an all-zero site stores scale 0.
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<float> &v)
+    {
+        (void)vh;
+        float m = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m = fmaxf(m, fmaxf(fabsf(v.c[a].re), fabsf(v.c[a].im)));
+        float inv = m > 0.f ? 1.0f / m : 0.f;
+        SpH q;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q.h[2 * a] = (half_t)(v.c[a].re * inv);
+            q.h[2 * a + 1] = (half_t)(v.c[a].im * inv);
+        }
+        q.s = m;
+        ((W16 *)base)[cb] = bitcast<W16>(q);
+    }
+};
+
+// Convert a vector between real types.
+template <typename To, typename From> __device__ __forceinline__ V3<To> vcast(const V3<From> &v)
+{
+    V3<To> w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w.c[a] = {(To)v.c[a].re, (To)v.c[a].im};
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// geometry: checkerboard index <-> coordinates, neighbours, staggered phases
+
+struct Geom {
+    int32_t n[4];   // Nx, Ny, Nz, Nt
+    int32_t vh;     // sites per parity
+};
+
+struct Site {
+    int32_t lex;        // lexicographic index
+    int32_t fwd[4];     // checkerboard index of x + mu
+    int32_t bwd[4];     // checkerboard index of x - mu
+    uint32_t negf;      // bit mu: phase of link (x, mu) is -1
+    uint32_t negb;      // bit mu: phase of link (x - mu, mu) is -1
+};
+
+// Lexicographic index of the site with checkerboard index cb and the given parity.
+__device__ __forceinline__ int lex_of(const Geom &g, int cb, int parity)
+{
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    int lex0 = 2 * cb;
+    int q = lex0 / nx;
+    int y = q % ny;
+    q /= ny;
+    int z = q % nz;
+    int t = q / nz;
+    return lex0 + ((y + z + t + parity) & 1);
+}
+
+// Coordinates of the site with checkerboard index cb and the given parity,
+// its eight neighbours and the signs of the eight links that touch it.
+__device__ __forceinline__ Site decode(const Geom &g, int cb, int parity)
+{
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2], nt = g.n[3];
+    int lex0 = 2 * cb;
+    int q = lex0 / nx;
+    int x0 = lex0 - q * nx;
+    int y = q % ny;
+    q /= ny;
+    int z = q % nz;
+    int t = q / nz;
+    int x = x0 + ((y + z + t + parity) & 1);
+    int lex = lex0 + (x - x0);
+    const int sy = nx, sz = nx * ny, st = nx * ny * nz;
+    Site s;
+    s.lex = lex;
+    s.fwd[0] = (x == nx - 1 ? lex - (nx - 1) : lex + 1) >> 1;
+    s.bwd[0] = (x == 0 ? lex + (nx - 1) : lex - 1) >> 1;
+    s.fwd[1] = (y == ny - 1 ? lex - (ny - 1) * sy : lex + sy) >> 1;
+    s.bwd[1] = (y == 0 ? lex + (ny - 1) * sy : lex - sy) >> 1;
+    s.fwd[2] = (z == nz - 1 ? lex - (nz - 1) * sz : lex + sz) >> 1;
+    s.bwd[2] = (z == 0 ? lex + (nz - 1) * sz : lex - sz) >> 1;
+    s.fwd[3] = (t == nt - 1 ? lex - (nt - 1) * st : lex + st) >> 1;
+    s.bwd[3] = (t == 0 ? lex + (nt - 1) * st : lex - st) >> 1;
+    // eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z);
+    // eta_mu does not depend on x_mu, so the backward link shares it, and the
+    // antiperiodic sign sits on t-links leaving t = Nt - 1.
+    uint32_t e1 = x & 1, e2 = (x + y) & 1, e3 = (x + y + z) & 1;
+    uint32_t eta = (e1 << 1) | (e2 << 2) | (e3 << 3);
+    s.negf = eta ^ ((t == nt - 1) ? 8u : 0u);
+    s.negb = eta ^ ((t == 0) ? 8u : 0u);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// reductions (wave64 shuffles, then LDS across the waves of a block)
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block; the result is valid in every thread.  blockDim.x must
+// be a multiple of 64 and at most 1024.  Fixed order, hence deterministic.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[16];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    return s;
+}
+
+// Called by every thread of every block after the block has written its
+// partial result: returns true in all threads of exactly one block, the last
+// to arrive, which then sees every partial.  The counter is reset by that
+// block so the next kernel can reuse it.
+__device__ __forceinline__ bool last_block(uint32_t *counter, uint32_t nblocks)
+{
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (t == nblocks - 1);
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// Fixed-order sum of n partials by one block (valid in every thread).
+__device__ __forceinline__ double sum_partials(const double *p, int n)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return block_sum(s);
+}
+
+}  // namespace lqs

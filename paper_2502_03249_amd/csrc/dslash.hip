@@ -1,0 +1,147 @@
+// dslash.hip -- the staggered hop D_{p,1-p} (eq. (1), Sec. 4.2) and its
+// adjoint, for one or several right-hand sides (Sec. 4.3, "NMULTI").
+//
+// One thread computes one output site for K right-hand sides: it streams the
+// four forward links of its own parity and the four backward links of the
+// other parity once (coalesced word-major arrays), and gathers the eight
+// neighbouring colour vectors, which nearby threads share through the caches.
+// The stencil is bound by HBM bandwidth (570 flop per site against 1584 bytes
+// in FP64), so there is no matrix-core path.
+#include "hop.hpp"
+
+namespace lqs {
+
+// gate_mode 0: always run; 1: only right-hand sides whose CG phase is
+// RUNNING; 2: only those with a pending FP64 residual update.
+__device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, int r)
+{
+    if (gate_mode == 0) return true;
+    if (gate_mode == 1) return gate[r].phase == CG_RUNNING;
+    return gate[r].reliable_pending != 0;
+}
+
+template <int P, int R, int K, bool DAG>
+__global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
+                                                  int64_t in_stride, char *out, int64_t out_stride,
+                                                  const CgState *gate, int gate_mode)
+{
+    typedef typename RealOf<P>::type T;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cb >= g.vh) return;
+    const int r0 = blockIdx.y * K;
+    bool active[K];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        active[j] = (r0 + j < nrhs) && gate_open(gate, gate_mode, r0 + j);
+        any |= active[j];
+    }
+    if (!any) return;
+    const Site s = decode(g, cb, parity);
+    V3<T> acc[K];
+    hop_site<P, R, K>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!active[j]) continue;
+        V3<T> o = acc[j];
+        if (DAG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o.c[a] = {-o.c[a].re, -o.c[a].im};
+        }
+        SpinorIO<P>::store(out + (r0 + j) * out_stride, g.vh, cb, o);
+    }
+}
+
+template <int P, int R, int K>
+static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs, const void *in, void *out,
+                     const CgState *gate, int gate_mode, int block, hipStream_t s)
+{
+    const int64_t stride = field_bytes(g, P, 1);
+    dim3 grid((g.vh + block - 1) / block, (nrhs + K - 1) / K);
+    if (dagger)
+        hipLaunchKernelGGL((hop_kernel<P, R, K, true>), grid, dim3(block), 0, s, g, L, parity, nrhs,
+                           (const char *)in, stride, (char *)out, stride, gate, gate_mode);
+    else
+        hipLaunchKernelGGL((hop_kernel<P, R, K, false>), grid, dim3(block), 0, s, g, L, parity, nrhs,
+                           (const char *)in, stride, (char *)out, stride, gate, gate_mode);
+    LQS_HIP(hipGetLastError());
+}
+
+template <int P, int R>
+static void launch_pr(const Geom &g, LinkRef L, int dagger, int parity, int nrhs, const void *in, void *out,
+                      const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
+{
+    switch (sh.rhs_per_thread) {
+    case 1: launch_k<P, R, 1>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
+    case 2: launch_k<P, R, 2>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
+    case 4: launch_k<P, R, 4>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
+    default: throw Error(LQS_EINVAL, "rhs_per_thread must be 1, 2 or 4");
+    }
+}
+
+void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger, int parity, int nrhs,
+                      const void *in, void *out, const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
+{
+    if (prec == F64 && recon == 18) launch_pr<F64, 18>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+    else if (prec == F64) launch_pr<F64, 12>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+    else if (prec == F32 && recon == 18) launch_pr<F32, 18>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+    else if (prec == F32) launch_pr<F32, 12>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+    else if (recon == 18) launch_pr<F16, 18>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+    else launch_pr<F16, 12>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
+}
+
+LaunchShape default_hop_shape(int prec, int nrhs)
+{
+    LaunchShape sh;
+    sh.block = 256;
+    sh.rhs_per_thread = nrhs >= 4 ? (prec == F64 ? 2 : 4) : (nrhs >= 2 ? 2 : 1);
+    return sh;
+}
+
+void launch_hop_shape(const Geom &g, LinkRef links, int prec, int recon, int dagger, int out_parity, int nrhs,
+                      const void *in, void *out, const CgState *gate, LaunchShape shape, hipStream_t s)
+{
+    launch_hop_gated(g, links, prec, recon, dagger, out_parity, nrhs, in, out, gate, gate ? 1 : 0, shape, s);
+}
+
+// ---------------------------------------------------------------------------
+// profiling of hop launches with HIP events on the launch stream
+
+void prof_begin(Ctx &ctx, hipStream_t s)
+{
+    if (!ctx.profiling) return;
+    if (ctx.prof_used == ctx.prof_events.size()) {
+        hipEvent_t a, b;
+        LQS_HIP(hipEventCreate(&a));
+        LQS_HIP(hipEventCreate(&b));
+        ctx.prof_events.push_back({a, b});
+        ctx.prof_keys.push_back({0, 0});
+        ctx.prof_sites.push_back(0);
+    }
+    LQS_HIP(hipEventRecord(ctx.prof_events[ctx.prof_used].first, s));
+}
+
+void prof_end(Ctx &ctx, int prec, int recon, int64_t sites, hipStream_t s)
+{
+    if (!ctx.profiling) return;
+    LQS_HIP(hipEventRecord(ctx.prof_events[ctx.prof_used].second, s));
+    ctx.prof_keys[ctx.prof_used] = {prec, recon == 12 ? 1 : 0};
+    ctx.prof_sites[ctx.prof_used] = sites;
+    ++ctx.prof_used;
+}
+
+void launch_hop(Ctx &ctx, const Gauge &gauge, int prec, int recon, int dagger, int out_parity, int nrhs,
+                const void *in, void *out, hipStream_t s, const CgState *gate)
+{
+    LaunchShape sh = default_hop_shape(prec, nrhs);
+    if (ctx.tuner) {
+        LaunchShape t;
+        if (ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, prec, recon, nrhs), t)) sh = t;
+    }
+    prof_begin(ctx, s);
+    launch_hop_gated(gauge.g, gauge.ref(prec, recon), prec, recon, dagger, out_parity, nrhs, in, out, gate,
+                     gate ? 1 : 0, sh, s);
+    prof_end(ctx, prec, recon, (int64_t)gauge.vh * nrhs, s);
+}
+
+}  // namespace lqs

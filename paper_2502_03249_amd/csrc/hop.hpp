@@ -1,0 +1,45 @@
+// hop.hpp -- eq. (1) of the paper evaluated at one output site for K
+// right-hand sides that share the links (Sec. 4.2 for the operator, Sec. 4.3
+// for applying it to several vectors with one read of each link).
+#pragma once
+#include "dev.hpp"
+#include "lqs_impl.hpp"
+
+namespace lqs {
+
+// acc[j] = sum_mu [eps_mu(x) U_{x,mu} in_j(x+mu) - eps_mu(x-mu) U^dag_{x-mu,mu} in_j(x-mu)]
+// for the site cb of parity `parity` (decoded into s).  Inactive right-hand
+// sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
+// the input field (parity 1 - parity); consecutive sides are in_stride bytes
+// apart.
+template <int P, int R, int K>
+__device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
+                                         const char *in, int64_t in_stride, const bool *active,
+                                         V3<typename RealOf<P>::type> *acc)
+{
+    typedef typename RealOf<P>::type T;
+    const char *lb = (const char *)L.base;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = vzero<T>();
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+        const bool nf = (s.negf >> mu) & 1;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!active[j]) continue;
+            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
+            accum(acc[j], mv(uf, v), nf);
+        }
+        const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
+        const bool nb = !((s.negb >> mu) & 1);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!active[j]) continue;
+            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
+            accum(acc[j], mdv(ub, v), nb);
+        }
+    }
+}
+
+}  // namespace lqs

@@ -1,0 +1,214 @@
+// lqs_impl.hpp -- internal declarations shared by the host runtime and the
+// kernel files: context and gauge objects, kernel argument blocks, the CG
+// state kept in device memory, and the launch entry points of each kernel file.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lqs.h"
+#include "dev.hpp"
+
+namespace lqs {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws Error; the C ABI layer maps it to a status.
+
+struct Error : std::runtime_error {
+    lqs_status status;
+    Error(lqs_status s, const std::string &msg) : std::runtime_error(msg), status(s) {}
+};
+
+#define LQS_HIP(call)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            throw ::lqs::Error(e_ == hipErrorOutOfMemory ? LQS_ENOMEM : LQS_EHIP,                        \
+                               std::string(#call) + ": " + hipGetErrorString(e_));                       \
+    } while (0)
+
+#define LQS_REQUIRE(cond, status, msg)                                                                   \
+    do {                                                                                                 \
+        if (!(cond)) throw ::lqs::Error((status), (msg));                                                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// CG state of one right-hand side, in device memory.  Kernels of an
+// iteration run only while state == RUNNING; the FP64 residual group runs
+// only while reliable_pending is set.  Scalars never leave the device during
+// the iteration; the host polls this record every few iterations.
+
+enum CgPhase : int32_t {
+    CG_RUNNING = 0,
+    CG_INNER_DONE = 1,  // iterated residual below target, FP64 check pending
+    CG_CONVERGED = 2,   // FP64 residual below target (final)
+    CG_BREAKDOWN = 3,   // p.Mp <= 0 (final)
+    CG_NONFINITE = 4,   // NaN / Inf in a scalar (final)
+    CG_MAXITER = 5,     // iteration cap reached, residual checked (final)
+};
+
+struct CgState {
+    double rho;        // |r|^2 of the iterated residual
+    double rho_old;    // |r|^2 before the last update (for beta)
+    double alpha, beta;
+    double stop2;      // tol^2 |b|^2
+    double max_rho;    // largest rho since the last FP64 residual update
+    double delta2;     // reliable-update threshold delta^2
+    double true_r2;    // last FP64 |b - M x|^2
+    double b2;         // |b|^2
+    int32_t phase;
+    int32_t iters;
+    int32_t since_rel;
+    int32_t rel_interval;  // 0: FP64 solver (no periodic updates)
+    int32_t reliable_pending;
+    int32_t nreliable;
+    int32_t restarts;
+    int32_t max_iter;
+    uint32_t counter[4];   // last-block counters, one per reduction site
+};
+
+enum { CNT_DOT = 0, CNT_UPDATE = 1, CNT_RESID = 2, CNT_MISC = 3 };
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+
+struct LinkRef {
+    const void *base;      // start of the 8 (mu, parity) blocks
+    int64_t block_bytes;   // bytes of one block = bytes_per_site * vh
+};
+
+struct FieldRef {
+    void *data;
+    int64_t rhs_stride;    // bytes between consecutive right-hand sides
+};
+
+// ---------------------------------------------------------------------------
+// library objects
+
+struct Tuner;
+
+struct Ctx {
+    int device = 0;
+    hipDeviceProp_t prop{};
+    int num_cu = 0;
+    bool tuning = false;
+    std::unique_ptr<Tuner> tuner;
+    // workspace buffers by slot, grown on demand, freed with the context
+    std::map<std::string, std::pair<void *, size_t>> ws;
+    // pinned host mirror of CG states
+    void *host_state = nullptr;
+    size_t host_state_bytes = 0;
+    // hop profiling: per (prec, recon) sums of event-timed launches
+    bool profiling = false;
+    struct ProfSlot {
+        int64_t launches = 0;
+        double ms = 0.0;
+        int64_t sites = 0;
+    } prof[3][2];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    std::vector<std::pair<int, int>> prof_keys;
+    std::vector<int64_t> prof_sites;
+    size_t prof_used = 0;
+
+    void *workspace(const std::string &slot, size_t bytes);
+    ~Ctx();
+};
+
+struct Gauge {
+    Ctx *ctx = nullptr;
+    Geom g{};
+    int64_t vh = 0;
+    void *fmt[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][recon==12]
+    LinkRef ref(int prec, int recon) const
+    {
+        const void *p = fmt[prec][recon == 12 ? 1 : 0];
+        LQS_REQUIRE(p != nullptr, LQS_EUNSUPPORTED, "gauge does not hold the requested link format");
+        return {p, (int64_t)link_block_bytes_per_site(prec, recon) * vh};
+    }
+    ~Gauge();
+};
+
+Geom make_geom(const int32_t dims[4]);
+int64_t field_bytes(const Geom &g, int prec, int nrhs);
+
+// ---------------------------------------------------------------------------
+// launch entry points (one kernel file each)
+
+// pack.hip
+void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, void *out, hipStream_t s);
+void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s);
+void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s);
+void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
+
+// dslash.hip
+struct LaunchShape {
+    int block = 256;       // threads per block
+    int rhs_per_thread = 1;
+};
+void launch_hop(Ctx &ctx, const Gauge &gauge, int prec, int recon, int dagger, int out_parity, int nrhs,
+                const void *in, void *out, hipStream_t s, const CgState *gate);
+LaunchShape default_hop_shape(int prec, int nrhs);
+void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger, int parity, int nrhs,
+                      const void *in, void *out, const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s);
+void launch_hop_shape(const Geom &g, LinkRef links, int prec, int recon, int dagger, int out_parity, int nrhs,
+                      const void *in, void *out, const CgState *gate, LaunchShape shape, hipStream_t s);
+
+// blas.hip -- the CG kernels (fused hop + epilogue, vector updates)
+struct CgVectors {
+    int prec;               // inner precision of p, q, t
+    int acc_prec;           // precision of x_lo and r (F64 in the plain solver)
+    int recon;              // inner link format
+    int nrhs;
+    double mass;
+    void *p, *q, *t;        // p, q even; t odd
+    void *r, *xlo;          // iterated residual and inner solution (even)
+    double *x, *b, *rhi;    // FP64: solution, source, FP64 residual (even)
+    void *t64;              // FP64 odd scratch (residual hop)
+    CgState *state;         // nrhs records
+    double *partials;       // nrhs * max_blocks
+    int max_blocks;
+};
+void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_t s);
+void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, bool with_reliable);
+int cg_partials_needed(const Gauge &gauge, int nrhs);
+
+// force.hip
+void launch_force(const Geom &g, LinkRef links64, const double *X, const double *Y, const double *psx,
+                  const double *psy, double coeff, int mode, double *out, hipStream_t s);
+
+// persistent.hip
+struct PersistentProblem {
+    const Gauge *gauge;
+    double mass;
+    const double *b;
+    double *x;
+};
+void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, const lqs_cg_params &prm,
+                      lqs_cg_stats *stats, hipStream_t s);
+
+// tune.cpp
+struct Tuner {
+    std::string path;
+    std::map<std::string, std::string> cache;  // key -> "block,rhs_per_thread"
+    explicit Tuner(const char *p);
+    bool lookup(const std::string &key, LaunchShape &out) const;
+    void store(const std::string &key, const LaunchShape &v);
+    void save() const;
+};
+std::string tune_key(const Ctx &ctx, const char *kernel, const Geom &g, int prec, int recon, int nrhs);
+
+// profiling hooks around a hop launch (no-ops unless ctx.profiling)
+void prof_begin(Ctx &ctx, hipStream_t s);
+void prof_end(Ctx &ctx, int prec, int recon, int64_t sites, hipStream_t s);
+
+}  // namespace lqs
+
+// The opaque C handles are the library objects themselves.
+struct lqs_ctx : lqs::Ctx {};
+struct lqs_gauge : lqs::Gauge {};

@@ -1,0 +1,146 @@
+// pack.hip -- layout conversions: canonical complex128 links into the native
+// word-major formats (FP64/FP32/FP16, 18 or 12 reals; the 12-real form keeps
+// rows 0 and 1 and the kernels rebuild row 2, Sec. 4.3), canonical colour
+// vectors into native single-parity fields and back, and precision changes
+// between native fields.  All are one thread per site, once per call.
+#include "lqs_impl.hpp"
+
+namespace lqs {
+
+template <int P, int R>
+__global__ void pack_links_kernel(Geom g, const double2 *canon, char *out, int64_t block_bytes)
+{
+    typedef typename RealOf<P>::type T;
+    const int64_t V = 2 * (int64_t)g.vh;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y >> 1, parity = blockIdx.y & 1;
+    if (cb >= g.vh) return;
+    const int lex = lex_of(g, cb, parity);
+    const double2 *src = canon + 9 * ((int64_t)mu * V + lex);
+    M3<T> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        double2 d = src[k];
+        u.e[k / 3][k % 3] = {(T)d.x, (T)d.y};
+    }
+    LinkIO<P, R>::store(out + (2 * mu + parity) * block_bytes, g.vh, cb, u);
+}
+
+template <int P, int R> static void pack_links_t(const Geom &g, const double *canon, void *out, hipStream_t s)
+{
+    const int64_t block_bytes = (int64_t)link_block_bytes_per_site(P, R) * g.vh;
+    dim3 grid((g.vh + 255) / 256, 8);
+    hipLaunchKernelGGL((pack_links_kernel<P, R>), grid, dim3(256), 0, s, g, (const double2 *)canon, (char *)out,
+                       block_bytes);
+    LQS_HIP(hipGetLastError());
+}
+
+void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, void *out, hipStream_t s)
+{
+    if (prec == F64 && recon == 18) pack_links_t<F64, 18>(g, canon, out, s);
+    else if (prec == F64) pack_links_t<F64, 12>(g, canon, out, s);
+    else if (prec == F32 && recon == 18) pack_links_t<F32, 18>(g, canon, out, s);
+    else if (prec == F32) pack_links_t<F32, 12>(g, canon, out, s);
+    else if (recon == 18) pack_links_t<F16, 18>(g, canon, out, s);
+    else pack_links_t<F16, 12>(g, canon, out, s);
+}
+
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ void field_pack_kernel(Geom g, const double2 *lex, int parity, char *out, int64_t rhs_stride)
+{
+    typedef typename RealOf<P>::type T;
+    const int64_t V = 2 * (int64_t)g.vh;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (cb >= g.vh) return;
+    const int l = lex_of(g, cb, parity);
+    const double2 *src = lex + 3 * (r * V + l);
+    V3<T> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v.c[a] = {(T)src[a].x, (T)src[a].y};
+    SpinorIO<P>::store(out + r * rhs_stride, g.vh, cb, v);
+}
+
+template <int P>
+__global__ void field_unpack_kernel(Geom g, const char *in, int64_t rhs_stride, int parity, double2 *lex)
+{
+    const int64_t V = 2 * (int64_t)g.vh;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (cb >= g.vh) return;
+    const int l = lex_of(g, cb, parity);
+    const auto v = SpinorIO<P>::load(in + r * rhs_stride, g.vh, cb);
+    double2 *dst = lex + 3 * (r * V + l);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dst[a] = make_double2((double)v.c[a].re, (double)v.c[a].im);
+}
+
+void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s)
+{
+    dim3 grid((g.vh + 255) / 256, out.nrhs);
+    const int64_t stride = field_bytes(g, out.prec, 1);
+    if (out.prec == F64)
+        hipLaunchKernelGGL(field_pack_kernel<F64>, grid, dim3(256), 0, s, g, (const double2 *)lex, out.parity,
+                           (char *)out.data, stride);
+    else if (out.prec == F32)
+        hipLaunchKernelGGL(field_pack_kernel<F32>, grid, dim3(256), 0, s, g, (const double2 *)lex, out.parity,
+                           (char *)out.data, stride);
+    else
+        hipLaunchKernelGGL(field_pack_kernel<F16>, grid, dim3(256), 0, s, g, (const double2 *)lex, out.parity,
+                           (char *)out.data, stride);
+    LQS_HIP(hipGetLastError());
+}
+
+void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s)
+{
+    dim3 grid((g.vh + 255) / 256, in.nrhs);
+    const int64_t stride = field_bytes(g, in.prec, 1);
+    if (in.prec == F64)
+        hipLaunchKernelGGL(field_unpack_kernel<F64>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
+                           in.parity, (double2 *)lex);
+    else if (in.prec == F32)
+        hipLaunchKernelGGL(field_unpack_kernel<F32>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
+                           in.parity, (double2 *)lex);
+    else
+        hipLaunchKernelGGL(field_unpack_kernel<F16>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
+                           in.parity, (double2 *)lex);
+    LQS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+
+template <int PI, int PO>
+__global__ void convert_kernel(int vh, const char *in, int64_t in_stride, char *out, int64_t out_stride)
+{
+    typedef typename RealOf<PO>::type TO;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (cb >= vh) return;
+    const auto v = SpinorIO<PI>::load(in + r * in_stride, vh, cb);
+    SpinorIO<PO>::store(out + r * out_stride, vh, cb, vcast<TO>(v));
+}
+
+template <int PI>
+static void convert_from(const Geom &g, int nrhs, const void *in, int prec_out, void *out, hipStream_t s)
+{
+    dim3 grid((g.vh + 255) / 256, nrhs);
+    const int64_t si = field_bytes(g, PI, 1), so = field_bytes(g, prec_out, 1);
+    if (prec_out == F64)
+        hipLaunchKernelGGL((convert_kernel<PI, F64>), grid, dim3(256), 0, s, g.vh, (const char *)in, si, (char *)out, so);
+    else if (prec_out == F32)
+        hipLaunchKernelGGL((convert_kernel<PI, F32>), grid, dim3(256), 0, s, g.vh, (const char *)in, si, (char *)out, so);
+    else
+        hipLaunchKernelGGL((convert_kernel<PI, F16>), grid, dim3(256), 0, s, g.vh, (const char *)in, si, (char *)out, so);
+    LQS_HIP(hipGetLastError());
+}
+
+void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s)
+{
+    if (prec_in == F64) convert_from<F64>(g, nrhs, in, prec_out, out, s);
+    else if (prec_in == F32) convert_from<F32>(g, nrhs, in, prec_out, out, s);
+    else convert_from<F16>(g, nrhs, in, prec_out, out, s);
+}
+
+}  // namespace lqs

@@ -1,0 +1,163 @@
+// tune.cpp -- launch-shape autotuner with a persistent cache.
+//
+// For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
+// times every candidate shape (threads per block x right-hand sides per
+// thread) with HIP events on the caller's stream, keeps the one with the
+// lowest median time, and stores it in a flat JSON object
+// {"key": "block,rhs_per_thread", ...} that later runs load.  Tuning runs
+// write only into library scratch buffers, never into caller memory.
+#include <algorithm>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "lqs_impl.hpp"
+
+namespace lqs {
+
+void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape sh, hipStream_t s);
+
+Tuner::Tuner(const char *p)
+{
+    if (!p) return;
+    path = p;
+    std::ifstream in(path);
+    if (!in) return;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string txt = ss.str();
+    // entries look like "key": "value"; keys and values hold no quotes
+    size_t pos = 0;
+    while (true) {
+        size_t k0 = txt.find('"', pos);
+        if (k0 == std::string::npos) break;
+        size_t k1 = txt.find('"', k0 + 1);
+        size_t v0 = txt.find('"', k1 + 1);
+        size_t v1 = v0 == std::string::npos ? v0 : txt.find('"', v0 + 1);
+        if (k1 == std::string::npos || v1 == std::string::npos) break;
+        cache[txt.substr(k0 + 1, k1 - k0 - 1)] = txt.substr(v0 + 1, v1 - v0 - 1);
+        pos = v1 + 1;
+    }
+}
+
+bool Tuner::lookup(const std::string &key, LaunchShape &out) const
+{
+    auto it = cache.find(key);
+    if (it == cache.end()) return false;
+    int b = 0, k = 0;
+    if (std::sscanf(it->second.c_str(), "%d,%d", &b, &k) != 2) return false;
+    if (b < 64 || b > 512 || (b & 63) || !(k == 1 || k == 2 || k == 4)) return false;
+    out.block = b;
+    out.rhs_per_thread = k;
+    return true;
+}
+
+void Tuner::store(const std::string &key, const LaunchShape &v)
+{
+    cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread);
+}
+
+void Tuner::save() const
+{
+    if (path.empty()) return;
+    std::ofstream out(path + ".tmp");
+    if (!out) return;
+    out << "{\n";
+    size_t i = 0;
+    for (const auto &kv : cache) {
+        out << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++i < cache.size() ? ",\n" : "\n");
+    }
+    out << "}\n";
+    out.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+std::string tune_key(const Ctx &ctx, const char *kernel, const Geom &g, int prec, int recon, int nrhs)
+{
+    std::ostringstream k;
+    k << ctx.prop.gcnArchName << "|" << kernel << "|" << g.n[0] << "x" << g.n[1] << "x" << g.n[2] << "x" << g.n[3]
+      << "|p" << prec << "|r" << recon << "|n" << nrhs;
+    std::string s = k.str();
+    std::replace(s.begin(), s.end(), '"', '_');
+    return s;
+}
+
+static std::vector<LaunchShape> candidates(int nrhs)
+{
+    std::vector<LaunchShape> c;
+    for (int k : {1, 2, 4}) {
+        if (k > nrhs) break;
+        for (int b : {64, 128, 256, 512}) c.push_back({b, k});
+    }
+    return c;
+}
+
+void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int recon, int nrhs, hipStream_t s)
+{
+    if (!ctx.tuner) return;
+    const std::string key = tune_key(ctx, kernel, gauge.g, prec, recon, nrhs);
+    LaunchShape found;
+    if (ctx.tuner->lookup(key, found)) return;
+    const bool is_dot = std::strcmp(kernel, "normal_dot") == 0;
+    const Geom &g = gauge.g;
+    const int64_t fb = field_bytes(g, prec, nrhs);
+    void *in = ctx.workspace("tune.in", fb);
+    void *out = ctx.workspace("tune.out", fb);
+    void *aux = ctx.workspace("tune.aux", fb);
+    LQS_HIP(hipMemsetAsync(in, 0, fb, s));
+    LQS_HIP(hipMemsetAsync(aux, 0, fb, s));
+    CgVectors v{};
+    CgState *st = nullptr;
+    std::vector<CgState> tmpl(nrhs);
+    if (is_dot) {
+        v.prec = prec;
+        v.recon = recon;
+        v.nrhs = nrhs;
+        v.mass = 0.1;
+        v.t = in;
+        v.p = aux;
+        v.q = out;
+        v.max_blocks = cg_partials_needed(gauge, nrhs);
+        v.partials = (double *)ctx.workspace("tune.partials", sizeof(double) * (size_t)v.max_blocks * nrhs);
+        st = (CgState *)ctx.workspace("tune.state", sizeof(CgState) * nrhs);
+        for (auto &S : tmpl) {
+            S = CgState{};
+            S.phase = CG_RUNNING;
+            S.rho = 1.0;
+        }
+        v.state = st;
+    }
+    hipEvent_t e0, e1;
+    LQS_HIP(hipEventCreate(&e0));
+    LQS_HIP(hipEventCreate(&e1));
+    const LinkRef L = gauge.ref(prec, recon);
+    float best = 1e30f;
+    LaunchShape best_shape = default_hop_shape(prec, nrhs);
+    for (const LaunchShape &c : candidates(nrhs)) {
+        std::vector<float> t;
+        for (int rep = 0; rep < 7; ++rep) {
+            if (is_dot)
+                LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
+            LQS_HIP(hipEventRecord(e0, s));
+            if (is_dot) launch_normal_dot_shape(gauge, v, c, s);
+            else launch_hop_gated(g, L, prec, recon, 0, 1, nrhs, in, out, nullptr, 0, c, s);
+            LQS_HIP(hipEventRecord(e1, s));
+            LQS_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            LQS_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep >= 2) t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        const float med = t[t.size() / 2];
+        if (med < best) {
+            best = med;
+            best_shape = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx.tuner->store(key, best_shape);
+    ctx.tuner->save();
+}
+
+}  // namespace lqs

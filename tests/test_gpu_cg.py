@@ -1,0 +1,118 @@
+"""GPU CG against the oracle: FP64, mixed precision, multi-RHS, warm start.
+
+The bar for every solve is the FP64 true residual ||b - M x|| / ||b|| <= tol,
+recomputed by the CPU oracle on the GPU's x; the GPU's own FP64 residual
+must agree with it, and x must agree with the oracle's solution to within
+kappa * tol (kappa = condition number bound (m^2 + 64) / m^2, since
+||D_eo D_oe|| <= 64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import field, gauge, lex_of, rel
+
+pytestmark = pytest.mark.gpu
+
+lqs = pytest.importorskip("paper_2502_03249_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lqs.Context(0)
+    yield c
+    c.close()
+
+
+def _solve(ctx, dims, U, mass, b, tol=1e-10, nrhs=1, **kw):
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xf = bf.like().zero_()
+    stats = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=tol, **kw)
+    return lex_of(ctx, xf, squeeze=(nrhs == 1)), stats
+
+
+def test_cg_fp64_config_4x4_haar(ctx):
+    """4^4, Haar links (seed 1000), Gaussian even source (seed 2000), m = 0.1."""
+    dims, mass = (4, 4, 4, 4), 0.1
+    U = synth.gauge(dims, "haar", seed=1000)
+    b = synth.source(dims, 0, seed=2000)
+    x, st = _solve(ctx, dims, U, mass, b)
+    assert st[0]["status"] == 0
+    tr = oracle.true_residual(dims, U, mass, b, x)
+    assert tr <= 1e-10 and abs(tr - st[0]["true_rel_residual"]) <= 1e-3 * tr + 1e-16
+    xo, so, _, _ = oracle.cg(dims, U, mass, b)
+    assert rel(x, xo) <= (mass ** 2 + 64) / mass ** 2 * 1e-10
+
+
+def test_cg_fp64_config_32x8_smooth(ctx):
+    """32^3 x 8, smooth links eps = 0.3 (seed 1001), Gaussian source (seed 2001), m = 0.02."""
+    dims, mass = (32, 32, 32, 8), 0.02
+    U = synth.gauge(dims, "smooth", seed=1001, eps=0.3)
+    b = synth.source(dims, 0, seed=2001)
+    x, st = _solve(ctx, dims, U, mass, b)
+    assert st[0]["status"] == 0
+    assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+    assert np.abs(x * (np.indices(x.shape[:4]).sum(0) % 2 == 1)[..., None]).max() == 0.0
+
+
+@pytest.mark.parametrize("prec,recon", [(lqs.F32, 18), (lqs.F16, 18), (lqs.F32, 12), (lqs.F16, 12)])
+def test_cg_mixed_precision_reaches_fp64_residual(ctx, prec, recon):
+    dims, mass = (16, 16, 16, 8), 0.02
+    U = synth.gauge(dims, "smooth", seed=41, eps=0.3)
+    b = synth.source(dims, 0, seed=42)
+    x, st = _solve(ctx, dims, U, mass, b, inner_prec=prec, inner_recon=recon, reliable_interval=100)
+    assert st[0]["status"] == 0, st
+    assert st[0]["reliable_updates"] >= 1
+    assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+    xo, _, _, _ = oracle.cg(dims, U, mass, b)
+    assert rel(x, xo) <= (mass ** 2 + 64) / mass ** 2 * 1e-10
+
+
+@pytest.mark.parametrize("prec", [lqs.F64, lqs.F32, lqs.F16])
+def test_cg_multi_rhs_each_column(ctx, prec):
+    """nrhs independent CGs sharing the links: every column reaches the residual on its own."""
+    dims, mass, nrhs = (8, 8, 8, 8), 0.05, 5
+    U = synth.gauge(dims, "smooth", seed=51, eps=0.3)
+    bs = np.stack([synth.source(dims, 0, seed=5100 + k) for k in range(nrhs)])
+    bs[2] *= 1e-3   # columns of very different norm converge at different iterations
+    x, st = _solve(ctx, dims, U, mass, bs, nrhs=nrhs, inner_prec=prec, reliable_interval=50)
+    assert len(st) == nrhs
+    for k in range(nrhs):
+        assert st[k]["status"] == 0
+        assert oracle.true_residual(dims, U, mass, bs[k], x[k]) <= 1e-10
+
+
+def test_cg_warm_start_resume(ctx):
+    dims, mass = (8, 8, 8, 8), 0.05
+    U = synth.gauge(dims, "haar", seed=61)
+    b = synth.source(dims, 0, seed=62)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xf = bf.like().zero_()
+    s1 = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-5)
+    assert s1[0]["status"] == 0 and s1[0]["true_rel_residual"] <= 1e-5
+    s2 = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, use_x0=True)
+    assert s2[0]["status"] == 0
+    x = lex_of(ctx, xf)
+    assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+
+
+def test_cg_max_iter_reports_not_converged(ctx):
+    dims, mass = (4, 4, 4, 4), 0.1
+    U = synth.gauge(dims, "haar", seed=1000)
+    b = synth.source(dims, 0, seed=2000)
+    x, st = _solve(ctx, dims, U, mass, b, max_iter=7)
+    assert st[0]["status"] == lqs.ENOTCONV
+    assert st[0]["iters"] >= 7
+    tr = oracle.true_residual(dims, U, mass, b, x)
+    assert abs(tr - st[0]["true_rel_residual"]) <= 1e-6 * tr
+
+
+def test_cg_zero_source(ctx):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge(dims, "haar", seed=1)
+    b = np.zeros((4, 4, 4, 4, 3), np.complex128)
+    x, st = _solve(ctx, dims, U, 0.1, b)
+    assert st[0]["status"] == 0 and np.abs(x).max() == 0.0
