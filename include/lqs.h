@@ -127,6 +127,13 @@ lqs_status lqs_field_pack(lqs_ctx *ctx, const int32_t dims[4], const double *lex
 lqs_status lqs_field_unpack(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double *lex,
                             void *stream);
 
+/* out[2*r], out[2*r+1] = real and imaginary part of sum_sites a_r^dag b_r for
+ * each right-hand side r (FP64 fields of one parity, nrhs each; out is a
+ * device array of 2*nrhs doubles).  Fixed-order reduction: the result does
+ * not depend on scheduling.  Used for the action phi^dag M^-1 phi. */
+lqs_status lqs_field_dot(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *a, const lqs_field *b, double *out,
+                         void *stream);
+
 /* ---- the operator ------------------------------------------------------ */
 
 /* out = D_{p,1-p} in: eq. (1) evaluated at the sites of parity p = out->parity,

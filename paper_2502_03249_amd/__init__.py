@@ -65,7 +65,8 @@ class LqsError(RuntimeError):
 _lib = None
 EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_create", "lqs_gauge_destroy",
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
-           "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result"]
+           "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
+           "lqs_field_dot"]
 
 
 def lib():
@@ -97,6 +98,7 @@ def lib():
     L.lqs_strerror.restype = ctypes.c_char_p
     L.lqs_last_error.argtypes = []
     L.lqs_last_error.restype = ctypes.c_char_p
+    L.lqs_field_dot.argtypes = [vp, i32p, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp, vp]
     L.lqs_profile_hops.argtypes = [vp, i32]
     L.lqs_profile_hops_result.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(d),
                                           ctypes.POINTER(ctypes.c_int64)]
@@ -296,6 +298,17 @@ def fermion_force(ctx, gauge, X, Y=None, coeff=1.0, mode=0, out=None, stream=Non
         yp = ctypes.c_void_p(Y.data.data_ptr())
     _check(lib().fermion_force(ctx.handle, gauge.handle, ctypes.c_void_p(X.data.data_ptr()), yp, float(coeff),
                                int(mode), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def field_dot(ctx, a, b, out=None, stream=None):
+    """sum_sites a^dag b per right-hand side (FP64 fields) as a complex128 device tensor of nrhs entries."""
+    assert a.prec == F64 and b.prec == F64
+    if out is None:
+        out = torch.empty(a.nrhs, dtype=torch.complex128, device=a.data.device)
+    ca, cb = a.c(), b.c()
+    _check(lib().lqs_field_dot(ctx.handle, _dims(a.dims), ctypes.byref(ca), ctypes.byref(cb),
+                               ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 

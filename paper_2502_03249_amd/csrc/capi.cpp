@@ -240,6 +240,21 @@ lqs_status lqs_field_unpack(lqs_ctx *ctx, const int32_t dims[4], const lqs_field
     });
 }
 
+lqs_status lqs_field_dot(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *a, const lqs_field *b, double *out,
+                         void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
+        check_dims(dims);
+        check_field(a, "a");
+        check_field(b, "b");
+        check_ptr(out, "out");
+        LQS_REQUIRE(a->prec == LQS_F64 && b->prec == LQS_F64, LQS_EUNSUPPORTED, "dot takes FP64 fields");
+        LQS_REQUIRE(a->nrhs == b->nrhs && a->parity == b->parity, LQS_EINVAL, "fields differ in nrhs or parity");
+        launch_field_dot(*ctx, make_geom(dims), a->nrhs, a->data, b->data, out, as_stream(stream));
+    });
+}
+
 static lqs_status dslash_common(lqs_ctx *ctx, const lqs_gauge *g, int32_t recon, const lqs_field *in, lqs_field *out,
                                 void *stream, int dagger)
 {

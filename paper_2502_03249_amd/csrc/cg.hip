@@ -141,10 +141,6 @@ __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, cons
         const int r = r0 + j;
         const double s = block_sum(dot[j]);
         if (threadIdx.x == 0) partials[(int64_t)r * max_blocks + blockIdx.x] = s;
-        if (last_block(&st[r].counter[CNT_DOT], gridDim.x)) {
-            const double pq = sum_partials(partials + (int64_t)r * max_blocks, gridDim.x);
-            if (threadIdx.x == 0) fin_alpha(st[r], pq);
-        }
     }
 }
 
@@ -184,10 +180,6 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
     }
     const double s = block_sum(local);
     if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
-    if (last_block(&S.counter[CNT_UPDATE], gridDim.x)) {
-        const double r2 = sum_partials(partials + (int64_t)rhs * max_blocks, gridDim.x);
-        if (threadIdx.x == 0) fin_update(S, r2);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,10 +282,6 @@ __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const 
         const int rr = r0 + j;
         const double s = block_sum(nrm[j]);
         if (threadIdx.x == 0) partials[(int64_t)rr * max_blocks + blockIdx.x] = s;
-        if (last_block(&st[rr].counter[CNT_RESID], gridDim.x)) {
-            const double r2 = sum_partials(partials + (int64_t)rr * max_blocks, gridDim.x);
-            if (threadIdx.x == 0) fin_residual(st[rr], r2, mode);
-        }
     }
 }
 
@@ -323,20 +311,54 @@ __global__ void __launch_bounds__(BLAS_BLOCK) init_kernel(int vh, const char *b,
     }
     const double s = block_sum(local);
     if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
-    if (last_block(&st[rhs].counter[CNT_MISC], gridDim.x)) {
-        const double b2 = sum_partials(partials + (int64_t)rhs * max_blocks, gridDim.x);
-        if (threadIdx.x == 0) {
-            CgState &S = st[rhs];
-            S.b2 = b2;
-            S.stop2 = S.stop2 * b2;  // the host stored tol^2 here
-            if (cold) {
-                S.rho = b2;
-                S.max_rho = b2;
-                S.true_r2 = b2;
-                S.phase = (b2 == 0.0) ? CG_CONVERGED : (isfinite(b2) ? CG_RUNNING : CG_NONFINITE);
-            }
+}
+
+// ---------------------------------------------------------------------------
+// Second reduction stage: one block per right-hand side sums the block
+// partials of the kernel before it in a fixed order and updates the scalars.
+// Running it as its own kernel (rather than in the last block of the
+// producer) needs no device-scope fence: the kernel boundary orders the
+// partials' stores before these loads.
+
+enum FinMode { FIN_DOT = 0, FIN_UPDATE = 1, FIN_RESID = 2, FIN_INIT = 3 };
+
+__global__ void __launch_bounds__(256) finalize_kernel(CgState *st, const double *partials, int max_blocks,
+                                                       int nblocks, int mode, int gate_mode, int sub)
+{
+    const int r = blockIdx.x;
+    CgState &S = st[r];
+    bool active = true;
+    if (mode == FIN_DOT || mode == FIN_UPDATE) active = S.phase == CG_RUNNING;
+    else if (mode == FIN_RESID) active = gate_mode == 0 || S.reliable_pending;
+    if (!active) return;
+    const double *p = partials + (int64_t)r * max_blocks;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += p[i];
+    const double v = block_sum(acc);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_DOT) {
+        fin_alpha(S, v);
+    } else if (mode == FIN_UPDATE) {
+        fin_update(S, v);
+    } else if (mode == FIN_RESID) {
+        fin_residual(S, v, sub);
+    } else {  // FIN_INIT, sub = cold start
+        S.b2 = v;
+        S.stop2 = S.stop2 * v;  // the host stored tol^2 here
+        if (sub) {
+            S.rho = v;
+            S.max_rho = v;
+            S.true_r2 = v;
+            S.phase = (v == 0.0) ? CG_CONVERGED : (isfinite(v) ? CG_RUNNING : CG_NONFINITE);
         }
     }
+}
+
+static void launch_finalize(const CgVectors &v, int nblocks, int mode, int gate_mode, int sub, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(v.nrhs), dim3(256), 0, s, v.state, (const double *)v.partials,
+                       v.max_blocks, nblocks, mode, gate_mode, sub);
+    LQS_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +417,7 @@ template <int PA, int PI> static void launch_blas(const Gauge &gauge, const CgVe
         hipLaunchKernelGGL((pupdate_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (const char *)v.r,
                            (char *)v.p, sa, si, (const CgState *)v.state);
     LQS_HIP(hipGetLastError());
+    if (which == 0) launch_finalize(v, grid.x, FIN_UPDATE, 0, 0, s);
 }
 
 template <int PA>
@@ -417,6 +440,7 @@ static void launch_residual_t(const Gauge &gauge, const CgVectors &v, int gate_m
                            (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
                            gate_mode, mode);
     LQS_HIP(hipGetLastError());
+    launch_finalize(v, grid.x, FIN_RESID, gate_mode, mode, s);
 }
 
 static void launch_residual(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
@@ -461,6 +485,7 @@ void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_
     else LQS_INIT(F32, F16);
 #undef LQS_INIT
     LQS_HIP(hipGetLastError());
+    launch_finalize(v, grid.x, FIN_INIT, 0, cold, s);
     if (use_x0) {
         residual_group(ctx, gauge, v, 0, 1, s);
         launch_convert(gauge.g, v.nrhs, v.acc_prec, v.r, v.prec, v.p, s);
@@ -482,6 +507,7 @@ void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, boo
     prof_end(ctx, v.prec, v.recon, gauge.vh * v.nrhs, s);
     // 2. q = m^2 p - D_eo t, <p,q>
     launch_normal_dot_shape(gauge, v, shd, s);
+    launch_finalize(v, (int)((gauge.vh + shd.block - 1) / shd.block), FIN_DOT, 0, 0, s);
     // 3. update
     if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 0, s);
     else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, s);

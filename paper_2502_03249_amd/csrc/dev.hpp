@@ -444,26 +444,9 @@ __device__ __forceinline__ double block_sum(double v)
     return s;
 }
 
-// Called by every thread of every block after the block has written its
-// partial result: returns true in all threads of exactly one block, the last
-// to arrive, which then sees every partial.  The counter is reset by that
-// block so the next kernel can reuse it.
-__device__ __forceinline__ bool last_block(uint32_t *counter, uint32_t nblocks)
-{
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == nblocks - 1);
-        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// Fixed-order sum of n partials by one block (valid in every thread).
+// Fixed-order sum of n partials by one block (valid in every thread); the
+// loads are device-coherent, for partials written by other blocks of the
+// same kernel behind a grid barrier.
 __device__ __forceinline__ double sum_partials(const double *p, int n)
 {
     double s = 0.0;

@@ -70,10 +70,7 @@ struct CgState {
     int32_t nreliable;
     int32_t restarts;
     int32_t max_iter;
-    uint32_t counter[4];   // last-block counters, one per reduction site
 };
-
-enum { CNT_DOT = 0, CNT_UPDATE = 1, CNT_RESID = 2, CNT_MISC = 3 };
 
 // ---------------------------------------------------------------------------
 // kernel argument blocks
@@ -145,6 +142,8 @@ void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, 
 void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s);
 void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s);
 void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
+struct Ctx;
+void launch_field_dot(Ctx &ctx, const Geom &g, int nrhs, const void *a, const void *b, double *out, hipStream_t s);
 
 // dslash.hip
 struct LaunchShape {

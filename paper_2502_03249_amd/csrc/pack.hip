@@ -144,3 +144,65 @@ void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int pr
 }
 
 }  // namespace lqs
+
+namespace lqs {
+
+// ---------------------------------------------------------------------------
+// sum_sites a^dag b per right-hand side, two fixed-order stages
+
+__global__ void __launch_bounds__(256) field_dot_kernel(int vh, const char *a, const char *b, int64_t stride,
+                                                        double *partials, int max_blocks)
+{
+    const int r = blockIdx.y;
+    double re = 0.0, im = 0.0;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<double> x = SpinorIO<F64>::load(a + r * stride, vh, cb);
+        const V3<double> y = SpinorIO<F64>::load(b + r * stride, vh, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Cx<double> t = cjmul(x.c[c], y.c[c]);
+            re += t.re;
+            im += t.im;
+        }
+    }
+    const double sr = block_sum(re);
+    const double si = block_sum(im);
+    double *pr = partials + (int64_t)r * 2 * max_blocks;
+    if (threadIdx.x == 0) {
+        pr[blockIdx.x] = sr;
+        pr[max_blocks + blockIdx.x] = si;
+    }
+}
+
+// second stage, one block per right-hand side, fixed order
+__global__ void __launch_bounds__(256) field_dot_final(const double *partials, int max_blocks, int nblocks, double *out)
+{
+    const int r = blockIdx.x;
+    const double *pr = partials + (int64_t)r * 2 * max_blocks;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+        re += pr[i];
+        im += pr[max_blocks + i];
+    }
+    const double tr = block_sum(re);
+    const double ti = block_sum(im);
+    if (threadIdx.x == 0) {
+        out[2 * r] = tr;
+        out[2 * r + 1] = ti;
+    }
+}
+
+void launch_field_dot(Ctx &ctx, const Geom &g, int nrhs, const void *a, const void *b, double *out, hipStream_t s)
+{
+    const int max_blocks = 512;
+    int blocks = (int)((g.vh + 255) / 256);
+    if (blocks > max_blocks) blocks = max_blocks;
+    double *partials = (double *)ctx.workspace("dot.partials", sizeof(double) * 2 * max_blocks * 16);
+    hipLaunchKernelGGL(field_dot_kernel, dim3(blocks, nrhs), dim3(256), 0, s, (int)g.vh, (const char *)a,
+                       (const char *)b, field_bytes(g, F64, 1), partials, max_blocks);
+    LQS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(field_dot_final, dim3(nrhs), dim3(256), 0, s, (const double *)partials, max_blocks, blocks, out);
+    LQS_HIP(hipGetLastError());
+}
+
+}  // namespace lqs

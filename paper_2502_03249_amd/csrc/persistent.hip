@@ -42,32 +42,41 @@ struct GridBar {
     uint32_t pad;
 };
 
+// Grid barrier.  On this GPU every XCD has its own L2, so making a block's
+// stores visible to blocks on other XCDs takes an agent-scope release (an L2
+// write-back) and reading theirs an agent-scope acquire (an L2 invalidate).
+// Each block pays exactly one of each per barrier: thread 0 releases, arrives
+// with a relaxed atomic, spins with relaxed loads (no cache maintenance per
+// poll), then acquires.  The last block to arrive resets the counter before
+// it publishes the new generation with a release store, so no block can
+// arrive at the next barrier before the reset is visible.
 __device__ __forceinline__ bool grid_sync(GridBar *gb, uint32_t nblocks, uint32_t &gen)
 {
     __shared__ uint32_t aborted;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == nblocks - 1) {
             __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            uint64_t spins = 0;
-            while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1ull << 26)) {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1u << 22)) {
                     __hip_atomic_store(&gb->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
-                if (__hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if ((spins & 255) == 0 && __hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         gen += 1;
         aborted = __hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    __threadfence();
     return aborted == 0;
 }
 
