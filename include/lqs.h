@@ -214,9 +214,11 @@ const char *lqs_last_error(void);
 
 /* Average duration in milliseconds of the hop kernels launched while
  * profiling was enabled, measured with HIP events on the launch stream.
- * lqs_profile_hops(ctx, 1) clears and starts, lqs_profile_hops(ctx, 0) stops. */
+ * lqs_profile_hops(ctx, 1) clears and starts, lqs_profile_hops(ctx, 0) stops.
+ * Launches shorter than min_ms are not counted (inside cg_solve, kernels
+ * queued after convergence return at once). */
 lqs_status lqs_profile_hops(lqs_ctx *ctx, int32_t enable);
-lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, int64_t *launches,
+lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, double min_ms, int64_t *launches,
                                    double *avg_ms, int64_t *sites_per_launch);
 
 #ifdef __cplusplus

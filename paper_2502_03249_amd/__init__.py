@@ -100,7 +100,7 @@ def lib():
     L.lqs_last_error.restype = ctypes.c_char_p
     L.lqs_field_dot.argtypes = [vp, i32p, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp, vp]
     L.lqs_profile_hops.argtypes = [vp, i32]
-    L.lqs_profile_hops_result.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(d),
+    L.lqs_profile_hops_result.argtypes = [vp, i32, i32, d, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(d),
                                           ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -316,8 +316,9 @@ def profile_hops(ctx, enable):
     _check(lib().lqs_profile_hops(ctx.handle, 1 if enable else 0))
 
 
-def profile_hops_result(ctx, prec, recon):
+def profile_hops_result(ctx, prec, recon, min_ms=0.0):
     n, ms, sites = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
-    _check(lib().lqs_profile_hops_result(ctx.handle, PREC[prec], int(recon), ctypes.byref(n), ctypes.byref(ms),
+    _check(lib().lqs_profile_hops_result(ctx.handle, PREC[prec], int(recon), float(min_ms), ctypes.byref(n),
+                                         ctypes.byref(ms),
                                          ctypes.byref(sites)))
     return int(n.value), float(ms.value), int(sites.value)

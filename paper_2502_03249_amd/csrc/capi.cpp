@@ -384,8 +384,8 @@ lqs_status lqs_profile_hops(lqs_ctx *ctx, int32_t enable)
     });
 }
 
-lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, int64_t *launches, double *avg_ms,
-                                   int64_t *sites_per_launch)
+lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, double min_ms, int64_t *launches,
+                                   double *avg_ms, int64_t *sites_per_launch)
 {
     return guard([&] {
         LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
@@ -395,6 +395,7 @@ lqs_status lqs_profile_hops_result(lqs_ctx *ctx, int32_t prec, int32_t recon, in
             float ms = 0.f;
             LQS_HIP(hipEventSynchronize(ctx->prof_events[i].second));
             LQS_HIP(hipEventElapsedTime(&ms, ctx->prof_events[i].first, ctx->prof_events[i].second));
+            if (ms < min_ms) continue;
             auto &slot = ctx->prof[ctx->prof_keys[i].first][ctx->prof_keys[i].second];
             slot.launches += 1;
             slot.ms += ms;

@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(BLAS_BLOCK) init_kernel(int vh, const char *b,
 
 enum FinMode { FIN_DOT = 0, FIN_UPDATE = 1, FIN_RESID = 2, FIN_INIT = 3 };
 
-__global__ void __launch_bounds__(256) finalize_kernel(CgState *st, const double *partials, int max_blocks,
+__global__ void __launch_bounds__(1024) finalize_kernel(CgState *st, const double *partials, int max_blocks,
                                                        int nblocks, int mode, int gate_mode, int sub)
 {
     const int r = blockIdx.x;
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(CgState *st, const double
 
 static void launch_finalize(const CgVectors &v, int nblocks, int mode, int gate_mode, int sub, hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(v.nrhs), dim3(256), 0, s, v.state, (const double *)v.partials,
+    hipLaunchKernelGGL(finalize_kernel, dim3(v.nrhs), dim3(1024), 0, s, v.state, (const double *)v.partials,
                        v.max_blocks, nblocks, mode, gate_mode, sub);
     LQS_HIP(hipGetLastError());
 }
