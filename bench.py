@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--only-hop", default=None, help="prec:recon, e.g. f64:18 -- hop launches only (profiling)")
     ap.add_argument("--only-copy", action="store_true", help="plain copy kernel only (counter calibration)")
     ap.add_argument("--dims", default=None, help="override lattice, e.g. 32,32,32,8")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure the other workloads (size sweep, multi-RHS, batches, force); one JSON line each")
     return ap.parse_args()
 
 
@@ -94,6 +96,10 @@ def main():
     dims = tuple(int(v) for v in a.dims.split(",")) if a.dims else DIMS
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if a.suite:
+        run_suite(a)
+        return
 
     if a.only_copy:
         n = 1 << 28   # 2 GiB of float64, copied 10 times
@@ -242,6 +248,171 @@ def main():
         "setup_s": round(setup_s, 1),
     }
     print(json.dumps(line))
+
+
+def run_suite(a):
+    """The other workloads, one JSON line per measurement (not the contract line).
+
+    hop size sweep (Fig. 3 analogue) | multi-vector hop on 32^4 and 32^3x8 (Table 2
+    analogue), default and autotuned shapes | 16-RHS block CG vs 16 single solves |
+    uneven three-lattice batch, persistent vs separate | 4^4 and 32^3x8 FP64 CG |
+    24^4 action, adjoint and force.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2502_03249_amd as lqs
+    from paper_2502_03249_amd import model
+    import synth
+
+    dev = torch.device("cuda", 0)
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def event_ms(fn, reps):
+        fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    ctx = lqs.Context(0)
+
+    def setup(dims, kind, lseed, sseeds, mass=None, formats=lqs.FMT_ALL):
+        U = synth.gauge(dims, kind, seed=lseed, eps=0.3)
+        g = lqs.Gauge(ctx, dims, torch.from_numpy(U).to(dev), formats)
+        srcs = np.stack([synth.source(dims, 0, seed=s) for s in sseeds])
+        b = lqs.Field.from_lex(ctx, torch.from_numpy(srcs).to(dev), 0)
+        torch.cuda.synchronize()
+        return U, g, b
+
+    # 1. hop size sweep (the hop at every format, standalone, stream events)
+    for dims in [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 8), (24, 24, 24, 24),
+                 (32, 32, 32, 32), (48, 48, 48, 12), (64, 64, 64, 16)]:
+        U, g, _ = setup(dims, "smooth", 1002, [7])
+        vh = int(np.prod(dims)) // 2
+        for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f16", 18), ("f16", 12)]:
+            pr = lqs.PREC[prec]
+            x = lqs.Field.from_lex(ctx, torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev), 1, pr)
+            y = x.like(parity=0)
+            ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 20)
+            mb = model.hop_model_bytes(pr, recon)
+            emit({"suite": "hop_size_sweep", "dims": dims, "prec": prec, "recon": recon, "us": round(1e3 * ms, 2),
+                  "model_GBps": round(mb * vh / ms / 1e6, 1), "GFLOPs": round(570 * vh / ms / 1e6, 1),
+                  "note": "lattice links fit in the 256 MB MALL" if mb * vh < 2.5e8 else "HBM"})
+        g.close()
+
+    # 2. multi-vector hop: 32^4 (the paper's Table 2 lattice) and 32^3x8 with 16 sources
+    for dims in [(32, 32, 32, 32), (32, 32, 32, 8)]:
+        U, g, _ = setup(dims, "smooth", 1001, [7])
+        vh = int(np.prod(dims)) // 2
+        srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
+        for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12)]:
+            pr = lqs.PREC[prec]
+            for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+                x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
+                y = x.like(parity=0)
+                for tuned in (False, True):
+                    ctx.set_tuning(tuned)
+                    ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
+                    emit({"suite": "nmulti", "dims": dims, "prec": prec, "recon": recon, "n": n, "tuned": tuned,
+                          "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
+                          "model_GBps": round(model.hop_model_bytes(pr, recon, n) * vh / ms / 1e6, 1)})
+                ctx.set_tuning(False)
+        g.close()
+
+    # 3. 16-RHS block CG on 32^3x8 (m 0.02) vs 16 single solves, FP32 inner + FP64 reliable updates
+    dims, mass = (32, 32, 32, 8), 0.02
+    U, g, b = setup(dims, "smooth", 1001, [2100 + k for k in range(16)])
+    x = b.like()
+    for prec in ("f32", "f16", "f64"):
+        st = []
+        t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.PREC[prec],
+                                                 reliable_interval=100)), 2)
+        singles = 0.0
+        for k in range(16):
+            bk = lqs.Field(dims, lqs.F64, 0, 1, data=b.data[k * lqs.field_bytes(dims, lqs.F64):
+                                                          (k + 1) * lqs.field_bytes(dims, lqs.F64)])
+            xk = bk.like()
+            singles += timed(lambda: lqs.cg_solve(ctx, [(g, mass, bk, xk.zero_())], tol=TOL,
+                                                  inner_prec=lqs.PREC[prec], reliable_interval=100), 1)
+        s = st[-1]
+        emit({"suite": "block_cg_16rhs", "dims": dims, "mass": mass, "inner": prec, "block_s": round(t, 4),
+              "sixteen_singles_s": round(singles, 4), "speedup": round(singles / t, 2),
+              "iters": [r["iters"] for r in s], "max_true_res": max(r["true_rel_residual"] for r in s),
+              "all_converged": all(r["status"] == 0 for r in s)})
+    g.close()
+
+    # 4. uneven batch: one persistent launch vs three multi-kernel solves
+    specs = [((16, 16, 16, 16), 0.05, 1031, 2031), ((24, 24, 24, 8), 0.02, 1032, 2032),
+             ((32, 32, 32, 8), 0.01, 1033, 2033)]
+    probs = []
+    for d_, m_, ls, ss in specs:
+        _, g_, b_ = setup(d_, "smooth", ls, [ss])
+        probs.append((g_, m_, b_, b_.like()))
+    for prec in ("f32", "f16", "f64"):
+        pr = lqs.PREC[prec]
+        st = []
+        tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
+                                                  tol=TOL, inner_prec=pr, reliable_interval=100,
+                                                  persistent=True)), 3)
+        ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
+                                        inner_prec=pr, reliable_interval=100), 3)
+        emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
+              "inner": prec, "persistent_s": round(tp, 5), "separate_s": round(ts, 5),
+              "speedup": round(ts / tp, 2), "iters": [r["iters"] for r in st[-1]],
+              "true_res": [r["true_rel_residual"] for r in st[-1]],
+              "all_converged": all(r["status"] == 0 for r in st[-1])})
+    for g_, _, _, _ in probs:
+        g_.close()
+
+    # 5. small-lattice and 32^3x8 FP64 CG (multi-kernel and persistent)
+    for dims, kind, ls, ss, mass in [((4, 4, 4, 4), "haar", 1000, 2000, 0.1), ((32, 32, 32, 8), "smooth", 1001, 2001, 0.02)]:
+        U, g, b = setup(dims, kind, ls, [ss])
+        x = b.like()
+        for persistent in (False, True):
+            st = []
+            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F64,
+                                                     persistent=persistent)), 3)
+            emit({"suite": "cg_fp64", "dims": dims, "mass": mass, "persistent": persistent, "s": round(t, 5),
+                  "iters": st[-1][0]["iters"], "true_res": st[-1][0]["true_rel_residual"]})
+        tm = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
+                                                  reliable_interval=100, inner_recon=12)), 3)
+        emit({"suite": "cg_mixed_f16", "dims": dims, "mass": mass, "s": round(tm, 5), "iters": st[-1][0]["iters"],
+              "true_res": st[-1][0]["true_rel_residual"]})
+        g.close()
+
+    # 6. differentiation: 24^4, m 0.05: action (CG), adjoint force
+    from paper_2502_03249_amd.autograd import staggered_action
+    dims, mass = (24, 24, 24, 24), 0.05
+    U = synth.gauge(dims, "smooth", seed=1004, eps=0.3)
+    Ut = torch.from_numpy(U).to(dev).requires_grad_(True)
+    phi = torch.from_numpy(synth.source(dims, 0, seed=2004)).to(dev).requires_grad_(True)
+
+    def fwd_bwd():
+        Ut.grad = None
+        phi.grad = None
+        S = staggered_action(Ut, phi, mass, ctx, project=True, tol=1e-10)
+        S.backward()
+    t = timed(fwd_bwd, 3)
+    g = lqs.Gauge(ctx, dims, Ut.detach(), lqs.fmt("f64", 18))
+    X = lqs.Field.from_lex(ctx, phi.detach(), 0)
+    out = torch.empty_like(Ut.detach())
+    ms = event_ms(lambda: lqs.fermion_force(ctx, g, X, None, 1.0, 0, out), 10)
+    emit({"suite": "force_24x4", "action_forward_backward_s": round(t, 4), "fermion_force_call_ms": round(ms, 4),
+          "note": "fermion_force = one D_oe hop + the outer-product/projection kernel"})
 
 
 if __name__ == "__main__":

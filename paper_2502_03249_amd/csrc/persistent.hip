@@ -456,29 +456,55 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
         S.phase = CG_RUNNING;
     }
     LQS_HIP(hipMemcpyAsync(dL, L.data(), sizeof(PLat) * nlat, hipMemcpyHostToDevice, s));
-    LQS_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(CgState) * nlat, hipMemcpyHostToDevice, s));
-    LQS_HIP(hipMemsetAsync(gb, 0, sizeof(GridBar), s));
 
     const void *fn = pick_kernel(prec, recon);
     int per_cu = 0;
     LQS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PBLOCK, 0));
     LQS_REQUIRE(per_cu >= 1, LQS_EUNSUPPORTED, "persistent kernel does not fit on a compute unit");
-    int grid = per_cu * ctx.num_cu;
-    if (ctx.tuner) {
-        LaunchShape t;
-        std::string key = tune_key(ctx, "persistent", L[0].g, prec, recon, nlat);
-        if (ctx.tuner->lookup(key, t) && t.block >= 64) grid = std::min(grid, (t.block / 64) * ctx.num_cu);
-    }
-    if (grid > tiles) grid = tiles;
     const int max_trips = prm.max_iter + 8;
     int ntiles = tiles;
-    void *args[] = {(void *)&dL, (void *)&nlat, (void *)&ntiles, (void *)&dS, (void *)&gb, (void *)&max_trips};
-    LQS_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PBLOCK), args, 0, s));
+    const std::vector<CgState> init = hs;
     GridBar hb{};
-    LQS_HIP(hipMemcpyAsync(hs.data(), dS, sizeof(CgState) * nlat, hipMemcpyDeviceToHost, s));
-    LQS_HIP(hipMemcpyAsync(&hb, gb, sizeof(GridBar), hipMemcpyDeviceToHost, s));
-    LQS_HIP(hipStreamSynchronize(s));
-    LQS_REQUIRE(hb.abort == 0, LQS_EHIP, "persistent solve: grid barrier timed out");
+    // One complete solve with `bpc` resident blocks per compute unit.
+    auto solve_once = [&](int bpc) {
+        int grid = std::min(bpc, per_cu) * ctx.num_cu;
+        if (grid > tiles) grid = tiles;
+        LQS_HIP(hipMemcpyAsync(dS, init.data(), sizeof(CgState) * nlat, hipMemcpyHostToDevice, s));
+        LQS_HIP(hipMemsetAsync(gb, 0, sizeof(GridBar), s));
+        void *args[] = {(void *)&dL, (void *)&nlat, (void *)&ntiles, (void *)&dS, (void *)&gb, (void *)&max_trips};
+        LQS_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PBLOCK), args, 0, s));
+        LQS_HIP(hipMemcpyAsync(hs.data(), dS, sizeof(CgState) * nlat, hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipMemcpyAsync(&hb, gb, sizeof(GridBar), hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipStreamSynchronize(s));
+        LQS_REQUIRE(hb.abort == 0, LQS_EHIP, "persistent solve: grid barrier timed out");
+    };
+    // The tuned value is the number of resident blocks per compute unit
+    // (stored as block = 64 * bpc); the key names every lattice of the batch.
+    std::string key = std::string(ctx.prop.gcnArchName) + "|persistent|p" + std::to_string(prec) + "|r" +
+                      std::to_string(recon);
+    for (const PLat &d : L)
+        key += "|" + std::to_string(d.g.n[0]) + "x" + std::to_string(d.g.n[1]) + "x" + std::to_string(d.g.n[2]) +
+               "x" + std::to_string(d.g.n[3]);
+    int bpc = 2;
+    LaunchShape t;
+    if (ctx.tuner && ctx.tuner->lookup(key, t)) {
+        bpc = t.block / 64;
+    } else if (ctx.tuning && ctx.tuner) {
+        double best = 1e30;
+        for (int c : {1, 2, 4, 8}) {
+            if (c > per_cu) break;
+            auto a0 = std::chrono::steady_clock::now();
+            solve_once(c);
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - a0).count();
+            if (dt < best) {
+                best = dt;
+                bpc = c;
+            }
+        }
+        ctx.tuner->store(key, LaunchShape{64 * bpc, 1});
+        ctx.tuner->save();
+    }
+    solve_once(bpc);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int l = 0; l < nlat; ++l) {
         const CgState &S = hs[l];

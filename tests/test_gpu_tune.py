@@ -1,0 +1,71 @@
+"""Autotuner: the sweep writes a cache, later contexts reuse it, results do not change."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import field, gauge, lex_of
+
+pytestmark = pytest.mark.gpu
+
+lqs = pytest.importorskip("paper_2502_03249_amd")
+
+
+def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "smooth", seed=91, eps=0.3)
+    srcs = np.stack([synth.source(dims, 1, seed=910 + k) for k in range(4)])
+    cache = str(tmp_path / "tune.json")
+
+    plain = lqs.Context(0)
+    g0 = gauge(plain, dims, U)
+    ref = lex_of(plain, lqs.dslash_apply(plain, g0, field(plain, dims, srcs, 1)), squeeze=False)
+
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    g1 = gauge(tuned, dims, U)
+    got = lex_of(tuned, lqs.dslash_apply(tuned, g1, field(tuned, dims, srcs, 1)), squeeze=False)
+    # a hop computes every site independently: the launch shape cannot change a bit
+    assert np.array_equal(got, ref)
+    b = synth.source(dims, 0, seed=92)
+    bf = field(tuned, dims, b, 0)
+    xf = bf.like().zero_()
+    st = lqs.cg_solve(tuned, [(g1, mass, bf, xf)], tol=1e-10, inner_prec=lqs.F32, reliable_interval=100)
+    assert st[0]["status"] == 0
+    assert oracle.true_residual(dims, U, mass, b, lex_of(tuned, xf)) <= 1e-10
+    tuned.close()
+
+    entries = json.load(open(cache))
+    keys = list(entries)
+    assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
+    assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
+    for v in entries.values():
+        blk, k = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4)
+
+    # the persistent multi-lattice solve tunes its resident blocks per compute unit
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    dims2 = (4, 6, 8, 10)
+    U2 = synth.gauge(dims2, "haar", seed=93)
+    b2 = synth.source(dims2, 0, seed=94)
+    probs = []
+    for d_, U_, b_ in ((dims, U, b), (dims2, U2, b2)):
+        gg = gauge(tuned, d_, U_)
+        bb = field(tuned, d_, b_, 0)
+        probs.append((gg, 0.1, bb, bb.like().zero_()))
+    st = lqs.cg_solve(tuned, probs, tol=1e-10, inner_prec=lqs.F32, reliable_interval=100, persistent=True)
+    assert all(s["status"] == 0 for s in st)
+    for (gg, m_, bb, xx), (d_, U_, b_) in zip(probs, ((dims, U, b), (dims2, U2, b2))):
+        assert oracle.true_residual(d_, U_, m_, b_, lex_of(tuned, xx)) <= 1e-10
+    tuned.close()
+    entries = json.load(open(cache))
+    assert any("|persistent|p1|r18|8x8x8x16|4x6x8x10" in k for k in entries)
+
+    # a new context loads the cache and does not need to tune again
+    again = lqs.Context(0, tune_cache=cache, tuning=True)
+    g2 = gauge(again, dims, U)
+    got2 = lex_of(again, lqs.dslash_apply(again, g2, field(again, dims, srcs, 1)), squeeze=False)
+    assert np.array_equal(got2, ref)
+    again.close()
+    assert json.load(open(cache)) == entries
