@@ -114,7 +114,9 @@ def main():
     t_setup = time.time()
     U = synth.gauge(dims, "smooth", seed=1002, eps=0.3)
     b = synth.source(dims, 0, seed=2002)
-    ctx = lqs.Context(0)
+    # The autotuner picks launch shapes on the first (untimed) use of each
+    # kernel configuration; timed runs only look them up.
+    ctx = lqs.Context(0, tuning=True)
     Ud = torch.from_numpy(U).to(dev)
     g = lqs.Gauge(ctx, dims, Ud, lqs.FMT_ALL)
     bf = lqs.Field.from_lex(ctx, torch.from_numpy(b).to(dev), 0)
@@ -184,12 +186,14 @@ def main():
     ok = all(s["status"] == 0 and s["true_rel_residual"] <= TOL for s in stats)
 
     # FP64 solve on the same system (untimed by the step loop, timed on its own)
+    other = lqs.F32 if inner == lqs.F16 else lqs.F16
+    for p_, r_, k_ in ((lqs.F64, 18, 0), (lqs.F64, 12, 0), (other, a.recon, a.reliable)):
+        solve(p_, r_, k_)  # warmup / tuning
     fp64 = [solve(lqs.F64, 18, 0) for _ in range(2)]
     fp64_s = min(t for t, _ in fp64)
     fp64_st = fp64[0][1]
     fp64_12 = [solve(lqs.F64, 12, 0) for _ in range(2)]
     fp64_12_s = min(t for t, _ in fp64_12)
-    other = lqs.F32 if inner == lqs.F16 else lqs.F16
     other_t, other_st = solve(other, a.recon, a.reliable)
 
     # standalone hop in every format
@@ -288,7 +292,8 @@ def run_suite(a):
         torch.cuda.synchronize()
         return s.elapsed_time(e) / reps
 
-    ctx = lqs.Context(0)
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    ctx = lqs.Context(0, tune_cache=os.path.join(ROOT, "gpurun_out", "tune_suite.json"))
 
     def setup(dims, kind, lseed, sseeds, mass=None, formats=lqs.FMT_ALL):
         U = synth.gauge(dims, kind, seed=lseed, eps=0.3)
@@ -333,6 +338,45 @@ def run_suite(a):
                 ctx.set_tuning(False)
         g.close()
 
+    # 2b. the paper's Table 2 storage: 32^4 in temporal gauge, 12-real links (6 links read per
+    #     site off the last time slice), FP64 and FP32, n = 1..16, tuned shapes
+    dims = (32, 32, 32, 32)
+    U = synth.gauge(dims, "smooth", seed=1001, eps=0.3)
+    Uf, _ = lqs.gauge_fix_temporal(ctx, dims, torch.from_numpy(U).to(dev))
+    g = lqs.Gauge(ctx, dims, Uf, lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+    vh = int(np.prod(dims)) // 2
+    srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
+    lps = 6 + 2 / dims[3]
+    ctx.set_tuning(True)
+    for prec, recon in [("f64", 12), ("f32", 12), ("f64", 18), ("f32", 18), ("f16", 12)]:
+        pr = lqs.PREC[prec]
+        for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+            x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
+            y = x.like(parity=0)
+            ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
+            emit({"suite": "nmulti_temporal", "dims": dims, "prec": prec, "recon": recon, "n": n,
+                  "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
+                  "model_GBps": round(model.hop_model_bytes(pr, recon, n, lps) * vh / ms / 1e6, 1)})
+    ctx.set_tuning(False)
+    g.close()
+    del Uf
+
+    # 2c. several masses on one Krylov space vs one solve per mass (64^3x16, FP64)
+    dims = DIMS
+    U, g, b = setup(dims, "smooth", 1002, [2002])
+    masses = [0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0]
+    xs = [b.like() for _ in masses]
+    st = []
+    t_ms = timed(lambda: st.append(lqs.cg_solve_multishift(ctx, g, masses, b, xs, tol=TOL)), 2)
+    t_sep = 0.0
+    for m_, x_ in zip(masses, xs):
+        t_sep += timed(lambda: lqs.cg_solve(ctx, [(g, m_, b, x_.zero_())], tol=TOL, inner_prec=lqs.F64), 1)
+    emit({"suite": "multishift", "dims": dims, "masses": masses, "multishift_s": round(t_ms, 4),
+          "separate_fp64_s": round(t_sep, 4), "speedup": round(t_sep / t_ms, 2),
+          "iters": [r["iters"] for r in st[-1]], "true_res": [r["true_rel_residual"] for r in st[-1]],
+          "all_converged": all(r["status"] == 0 for r in st[-1])})
+    g.close()
+
     # 3. 16-RHS block CG on 32^3x8 (m 0.02) vs 16 single solves, FP32 inner + FP64 reliable updates
     dims, mass = (32, 32, 32, 8), 0.02
     U, g, b = setup(dims, "smooth", 1001, [2100 + k for k in range(16)])
@@ -362,16 +406,18 @@ def run_suite(a):
     for d_, m_, ls, ss in specs:
         _, g_, b_ = setup(d_, "smooth", ls, [ss])
         probs.append((g_, m_, b_, b_.like()))
-    for prec in ("f32", "f16", "f64"):
+    for prec, tuned in (("f32", False), ("f32", True), ("f16", False), ("f16", True), ("f64", False)):
         pr = lqs.PREC[prec]
         st = []
+        ctx.set_tuning(tuned)
         tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
                                                   tol=TOL, inner_prec=pr, reliable_interval=100,
                                                   persistent=True)), 3)
+        ctx.set_tuning(False)
         ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
                                         inner_prec=pr, reliable_interval=100), 3)
         emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
-              "inner": prec, "persistent_s": round(tp, 5), "separate_s": round(ts, 5),
+              "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5), "separate_s": round(ts, 5),
               "speedup": round(ts / tp, 2), "iters": [r["iters"] for r in st[-1]],
               "true_res": [r["true_rel_residual"] for r in st[-1]],
               "all_converged": all(r["status"] == 0 for r in st[-1])})
@@ -394,7 +440,22 @@ def run_suite(a):
               "true_res": st[-1][0]["true_rel_residual"]})
         g.close()
 
-    # 6. differentiation: 24^4, m 0.05: action (CG), adjoint force
+    # 6. reliable-update interval K and threshold delta for the 64^3x16 FP16 solve
+    dims, mass = DIMS, MASS
+    U, g, b = setup(dims, "smooth", 1002, [2002])
+    x = b.like()
+    for K in (50, 100, 200, 400):
+        for delta in (0.1, 0.05, 0.01):
+            st = []
+            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
+                                                     inner_recon=12, reliable_interval=K, reliable_delta=delta)), 2)
+            r = st[-1][0]
+            emit({"suite": "reliable_sweep", "dims": dims, "K": K, "delta": delta, "s": round(t, 5),
+                  "iters": r["iters"], "reliable_updates": r["reliable_updates"],
+                  "true_res": r["true_rel_residual"], "status": r["status"]})
+    g.close()
+
+    # 7. differentiation: 24^4, m 0.05: action (CG), adjoint force
     from paper_2502_03249_amd.autograd import staggered_action
     dims, mass = (24, 24, 24, 24), 0.05
     U = synth.gauge(dims, "smooth", seed=1004, eps=0.3)

@@ -84,6 +84,10 @@ typedef enum { LQS_F64 = 0, LQS_F32 = 1, LQS_F16 = 2 } lqs_prec;
  * third row rebuilt on the fly as conj(row0 x row1), Sec. 4.3). */
 #define LQS_FMT(prec, recon) (1u << (2 * (unsigned)(prec) + ((recon) == 12 ? 1u : 0u)))
 #define LQS_FMT_ALL 0x3Fu
+/* Flag for lqs_gauge_create: the links are in temporal gauge, U_t(x) = 1 for
+ * every site with t < Nt-1 (Sec. 4.3); the hop then reads 6 links per site
+ * instead of 8 off the last time slice.  Checked at creation. */
+#define LQS_TEMPORAL_GAUGE 0x100u
 
 typedef struct lqs_ctx lqs_ctx;
 typedef struct lqs_gauge lqs_gauge;
@@ -109,12 +113,22 @@ void lqs_ctx_destroy(lqs_ctx *ctx);
 lqs_status lqs_set_tuning(lqs_ctx *ctx, int32_t enable);
 
 /* Pack a canonical link field into the formats of the `formats` bitmask
- * (LQS_FMT(LQS_F64, 18) is always added).  `links` is read on `stream`; the
- * call returns once packing has been enqueued.  Links must be SU(3) for the
+ * (LQS_FMT(LQS_F64, 18) is always added; LQS_TEMPORAL_GAUGE may be or-ed in).
+ * `links` is read on `stream`; the call returns once packing has been
+ * enqueued (with LQS_TEMPORAL_GAUGE it synchronises `stream` to check the
+ * gauge condition to 1e-12, else LQS_EINVAL).  Links must be SU(3) for the
  * 12-real formats to reproduce them.  Fails with LQS_EINVAL on odd extents. */
 lqs_status lqs_gauge_create(lqs_ctx *ctx, const int32_t dims[4], const double *links, uint32_t formats,
                             void *stream, lqs_gauge **out);
 void lqs_gauge_destroy(lqs_gauge *g);
+
+/* Temporal gauge fixing (Sec. 4.3): G(x, 0) = 1, G(x, t+1) = G(x, t) U_t(x, t)
+ * (rows re-orthonormalised, det 1), out_mu(x) = G(x) U_mu(x) G(x + mu)^dag,
+ * with out_t(x) set to exactly 1 for t < Nt-1.  links, out: canonical link
+ * layout (device, must not overlap); G: device complex128 [Nt][Nz][Ny][Nx][3][3].
+ * D[out] = G D[links] G^dag, so M[out] (G x) = G M[links] x.  Asynchronous. */
+lqs_status lqs_gauge_fix_temporal(lqs_ctx *ctx, const int32_t dims[4], const double *links, double *out, double *G,
+                                  void *stream);
 
 /* Bytes of one native field of nrhs right-hand sides. */
 lqs_status lqs_field_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs, size_t *bytes);
@@ -170,7 +184,7 @@ typedef struct {
     int32_t inner_prec;        /* LQS_F64: plain FP64 CG; LQS_F32/LQS_F16: mixed precision */
     int32_t inner_recon;       /* 18 or 12: link format of the inner operator              */
     int32_t reliable_interval; /* mixed: FP64 residual update every K iterations (0: 100)   */
-    double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r|| (0: 0.1)      */
+    double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r|| (0: 0.05)     */
     int32_t use_x0;            /* 1: start from x                                           */
     int32_t persistent;        /* 1: all problems in one cooperative launch (nrhs == 1)    */
 } lqs_cg_params;
@@ -191,6 +205,19 @@ typedef struct {
  * cooperative launches (else LQS_EUNSUPPORTED). */
 lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const lqs_cg_params *params,
                     lqs_cg_stats *stats, void *stream);
+
+/* Several masses on one Krylov space: x_i = (m_i^2 - D_eo D_oe)^-1 b for
+ * i < nmass (multi-shift CG; the systems differ by the shifts m_i^2 - m_0^2
+ * of the smallest mass m_0).  FP64 only: params->inner_prec must be LQS_F64
+ * and params->persistent 0; use_x0 is ignored (x_i start from zero).  b is an
+ * FP64 native even field (nrhs 1); x is a host array of nmass device pointers
+ * to FP64 native even fields, overwritten.  Every x_i is finally checked
+ * against its own FP64 true residual and refined by a warm-started CG when
+ * the shared recurrence ended above tol.  stats: nmass entries; iters counts
+ * the shared iterations while system i was active plus refinement iterations.
+ * nmass in 1..17, masses finite and >= 0. */
+lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, const double *masses, const double *b,
+                               double *const *x, const lqs_cg_params *params, lqs_cg_stats *stats, void *stream);
 
 /* ---- the derivative ---------------------------------------------------- */
 

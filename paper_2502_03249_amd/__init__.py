@@ -30,6 +30,7 @@ def fmt(prec, recon):
 
 
 FMT_ALL = 0x3F
+TEMPORAL_GAUGE = 0x100
 
 
 class LqsField(ctypes.Structure):
@@ -66,7 +67,7 @@ _lib = None
 EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_create", "lqs_gauge_destroy",
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
            "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
-           "lqs_field_dot"]
+           "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal"]
 
 
 def lib():
@@ -87,6 +88,7 @@ def lib():
     L.lqs_gauge_destroy.argtypes = [vp]
     L.lqs_gauge_destroy.restype = None
     L.lqs_field_bytes.argtypes = [i32p, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lqs_gauge_fix_temporal.argtypes = [vp, i32p, vp, vp, vp, vp]
     L.lqs_field_pack.argtypes = [vp, i32p, vp, ctypes.POINTER(LqsField), vp]
     L.lqs_field_unpack.argtypes = [vp, i32p, ctypes.POINTER(LqsField), vp, vp]
     L.dslash_apply.argtypes = [vp, vp, i32, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp]
@@ -94,6 +96,8 @@ def lib():
     L.cg_solve.argtypes = [vp, i32, ctypes.POINTER(LqsProblem), ctypes.POINTER(LqsCgParams),
                            ctypes.POINTER(LqsCgStats), vp]
     L.fermion_force.argtypes = [vp, vp, vp, vp, d, i32, vp, vp]
+    L.cg_solve_multishift.argtypes = [vp, vp, i32, ctypes.POINTER(d), vp, ctypes.POINTER(vp),
+                                      ctypes.POINTER(LqsCgParams), ctypes.POINTER(LqsCgStats), vp]
     L.lqs_strerror.argtypes = [i32]
     L.lqs_strerror.restype = ctypes.c_char_p
     L.lqs_last_error.argtypes = []
@@ -190,6 +194,17 @@ class Gauge:
             pass
 
 
+def gauge_fix_temporal(ctx, dims, links, stream=None):
+    """Temporal gauge (U_t = 1 off the last slice): returns (fixed links, G), canonical complex128 tensors."""
+    assert links.is_cuda and links.dtype == torch.complex128 and links.is_contiguous()
+    out = torch.empty_like(links)
+    G = torch.empty(links.shape[1:], dtype=torch.complex128, device=links.device)
+    _check(lib().lqs_gauge_fix_temporal(ctx.handle, _dims(dims), ctypes.c_void_p(links.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                        _stream(stream)))
+    return out, G
+
+
 class Field:
     """A native single-parity field of nrhs right-hand sides (device memory owned by torch)."""
 
@@ -281,6 +296,23 @@ def cg_solve(ctx, problems, tol=1e-10, max_iter=10000, inner_prec=F64, inner_rec
                       float(reliable_delta), 1 if use_x0 else 0, 1 if persistent else 0)
     stats = (LqsCgStats * total)()
     st = lib().cg_solve(ctx.handle, n, arr, ctypes.byref(prm), stats, _stream(stream))
+    if st < 0 and st not in (EBREAKDOWN, ENONFINITE):
+        _check(st)
+    return [s.as_dict() for s in stats]
+
+
+def cg_solve_multishift(ctx, gauge, masses, b, xs, tol=1e-10, max_iter=10000, inner_recon=18, stream=None):
+    """x_i = (m_i^2 - D_eo D_oe)^-1 b for every mass on one Krylov space (FP64); returns per-mass stats."""
+    n = len(masses)
+    assert len(xs) == n and b.prec == F64 and b.parity == 0 and b.nrhs == 1
+    for x in xs:
+        assert x.prec == F64 and x.parity == 0 and x.nrhs == 1
+    m = (ctypes.c_double * n)(*[float(v) for v in masses])
+    ptrs = (ctypes.c_void_p * n)(*[x.data.data_ptr() for x in xs])
+    prm = LqsCgParams(float(tol), int(max_iter), F64, int(inner_recon), 0, 0.0, 0, 0)
+    stats = (LqsCgStats * n)()
+    st = lib().cg_solve_multishift(ctx.handle, gauge.handle, n, m, ctypes.c_void_p(b.data.data_ptr()), ptrs,
+                                   ctypes.byref(prm), stats, _stream(stream))
     if st < 0 and st not in (EBREAKDOWN, ENONFINITE):
         _check(st)
     return [s.as_dict() for s in stats]

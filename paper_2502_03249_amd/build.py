@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblqs.so")
-SOURCES = ["capi.cpp", "tune.cpp", "pack.hip", "dslash.hip", "cg.hip", "force.hip", "persistent.hip"]
+SOURCES = ["capi.cpp", "tune.cpp", "pack.hip", "dslash.hip", "cg.hip", "force.hip", "persistent.hip",
+           "multishift.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -187,14 +187,20 @@ lqs_status lqs_gauge_create(lqs_ctx *ctx, const int32_t dims[4], const double *l
         LQS_REQUIRE(ctx != nullptr && out != nullptr, LQS_EINVAL, "ctx or out is NULL");
         check_dims(dims);
         check_ptr(links, "links");
-        LQS_REQUIRE((formats & ~LQS_FMT_ALL) == 0, LQS_EINVAL, "unknown format bits");
+        LQS_REQUIRE((formats & ~(LQS_FMT_ALL | LQS_TEMPORAL_GAUGE)) == 0, LQS_EINVAL, "unknown format bits");
         LQS_HIP(hipSetDevice(ctx->device));
-        formats |= LQS_FMT(LQS_F64, 18);
+        const bool temporal = (formats & LQS_TEMPORAL_GAUGE) != 0;
+        if (temporal) {
+            const double v = temporal_gauge_violation(*ctx, make_geom(dims), links, as_stream(stream));
+            LQS_REQUIRE(v <= 1e-12, LQS_EINVAL, "links are not in temporal gauge (U_t != 1 off the last slice)");
+        }
+        formats = (formats & LQS_FMT_ALL) | LQS_FMT(LQS_F64, 18);
         auto *g = new lqs_gauge();
         try {
             g->ctx = ctx;
             g->g = make_geom(dims);
             g->vh = g->g.vh;
+            g->temporal = temporal;
             for (int prec = 0; prec < 3; ++prec)
                 for (int rc = 0; rc < 2; ++rc) {
                     const int recon = rc ? 12 : 18;
@@ -216,6 +222,24 @@ void lqs_gauge_destroy(lqs_gauge *g)
     if (!g) return;
     (void)hipDeviceSynchronize();
     delete g;
+}
+
+lqs_status lqs_gauge_fix_temporal(lqs_ctx *ctx, const int32_t dims[4], const double *links, double *out, double *G,
+                                  void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
+        check_dims(dims);
+        check_ptr(links, "links");
+        check_ptr(out, "out");
+        check_ptr(G, "G");
+        const Geom g = make_geom(dims);
+        const int64_t lb = 2 * (int64_t)g.vh * 4 * 9 * 16;
+        const char *a = (const char *)links, *o = (const char *)out;
+        LQS_REQUIRE(a + lb <= o || o + lb <= a, LQS_EINVAL, "links and out overlap");
+        LQS_HIP(hipSetDevice(ctx->device));
+        launch_gauge_fix_temporal(g, links, out, G, as_stream(stream));
+    });
 }
 
 lqs_status lqs_field_pack(lqs_ctx *ctx, const int32_t dims[4], const double *lex, const lqs_field *out, void *stream)
@@ -336,6 +360,38 @@ lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const
         int n = 0;
         for (int i = 0; i < nprob; ++i) n += probs[i].nrhs;
         for (int i = 0; i < n; ++i) {
+            const lqs_status si = stats[i].status;
+            if (si < 0 && (worst >= 0 || si < worst)) worst = si;
+            else if (worst == LQS_OK && si > 0) worst = si;
+        }
+    });
+    return st != LQS_OK ? st : worst;
+}
+
+lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, const double *masses, const double *b,
+                               double *const *x, const lqs_cg_params *params, lqs_cg_stats *stats, void *stream)
+{
+    lqs_status worst = LQS_OK;
+    lqs_status st = guard([&] {
+        LQS_REQUIRE(ctx != nullptr && g != nullptr, LQS_EINVAL, "ctx or gauge is NULL");
+        LQS_REQUIRE(nmass >= 1 && nmass <= 17, LQS_EINVAL, "nmass must be in 1..17");
+        LQS_REQUIRE(masses != nullptr && x != nullptr && params != nullptr && stats != nullptr, LQS_EINVAL,
+                    "masses, x, params or stats is NULL");
+        const lqs_cg_params &p = *params;
+        LQS_REQUIRE(p.tol > 0 && std::isfinite(p.tol), LQS_EINVAL, "tol must be positive");
+        LQS_REQUIRE(p.max_iter >= 1, LQS_EINVAL, "max_iter must be >= 1");
+        LQS_REQUIRE(p.inner_recon == 18 || p.inner_recon == 12, LQS_EINVAL, "inner_recon must be 18 or 12");
+        LQS_REQUIRE(p.inner_prec == LQS_F64 && !p.persistent, LQS_EUNSUPPORTED, "multi-shift CG runs in FP64");
+        check_ptr(b, "b");
+        for (int i = 0; i < nmass; ++i) {
+            LQS_REQUIRE(std::isfinite(masses[i]) && masses[i] >= 0, LQS_EINVAL, "masses must be finite and >= 0");
+            check_ptr(x[i], "x[i]");
+            for (int j = 0; j < i; ++j) LQS_REQUIRE(x[i] != x[j], LQS_EINVAL, "solution fields must be distinct");
+        }
+        (void)g->ref(LQS_F64, p.inner_recon);
+        LQS_HIP(hipSetDevice(ctx->device));
+        multishift_solve(*ctx, *g, nmass, masses, b, x, p, stats, as_stream(stream));
+        for (int i = 0; i < nmass; ++i) {
             const lqs_status si = stats[i].status;
             if (si < 0 && (worst >= 0 || si < worst)) worst = si;
             else if (worst == LQS_OK && si > 0) worst = si;

@@ -97,7 +97,7 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 // ---------------------------------------------------------------------------
 // 2. q = m^2 p - D_eo t, <p, q>  (output parity even; t odd)
 
-template <int P, int R, int K>
+template <int P, int R, int K, bool TG>
 __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, double m2, CgState *st, double *partials,
                                                          int max_blocks, int nrhs)
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, cons
     V3<T> acc[K];
     if (valid) {
         const Site s = decode(g, cb, 0);
-        hop_site<P, R, K>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
+        hop_site<P, R, K, TG>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -385,12 +385,18 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const LinkRef L = gauge.ref(P, R);
     dim3 grid((g.vh + sh.block - 1) / sh.block, (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread);
     const double m2 = v.mass * v.mass;
-#define LQS_ND(K)                                                                                                 \
-    hipLaunchKernelGGL((normal_dot_kernel<P, R, K>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,         \
+#define LQS_ND(K, TG)                                                                                             \
+    hipLaunchKernelGGL((normal_dot_kernel<P, R, K, TG>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
                        (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs)
-    if (sh.rhs_per_thread == 1) LQS_ND(1);
-    else if (sh.rhs_per_thread == 2) LQS_ND(2);
-    else LQS_ND(4);
+    if (L.temporal) {
+        if (sh.rhs_per_thread == 1) LQS_ND(1, true);
+        else if (sh.rhs_per_thread == 2) LQS_ND(2, true);
+        else LQS_ND(4, true);
+    } else {
+        if (sh.rhs_per_thread == 1) LQS_ND(1, false);
+        else if (sh.rhs_per_thread == 2) LQS_ND(2, false);
+        else LQS_ND(4, false);
+    }
 #undef LQS_ND
     LQS_HIP(hipGetLastError());
 }
@@ -461,7 +467,7 @@ static void launch_accumulate(const Gauge &gauge, const CgVectors &v, int gated,
 }
 
 // The FP64 residual group: x += x_lo (mixed), t64 = D_oe x, residual kernel.
-static void residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+void cg_residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
 {
     (void)ctx;
     if (v.acc_prec != F64 && mode == 0) launch_accumulate(gauge, v, gate_mode == 2 ? 1 : 0, s);
@@ -487,7 +493,7 @@ void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_
     LQS_HIP(hipGetLastError());
     launch_finalize(v, grid.x, FIN_INIT, 0, cold, s);
     if (use_x0) {
-        residual_group(ctx, gauge, v, 0, 1, s);
+        cg_residual_group(ctx, gauge, v, 0, 1, s);
         launch_convert(gauge.g, v.nrhs, v.acc_prec, v.r, v.prec, v.p, s);
     }
 }
@@ -513,7 +519,7 @@ void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, boo
     else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, s);
     else launch_blas<F32, F16>(gauge, v, 0, s);
     // FP64 residual group (gated)
-    if (with_reliable) residual_group(ctx, gauge, v, 2, 0, s);
+    if (with_reliable) cg_residual_group(ctx, gauge, v, 2, 0, s);
     // 4. p = r + beta p
     if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 1, s);
     else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 1, s);
@@ -574,7 +580,7 @@ void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs
     }
     CgState *hs[2] = {(CgState *)ctx.host_state, (CgState *)((char *)ctx.host_state + sbytes)};
     const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
-    const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.1) : 0.0;
+    const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.05) : 0.0;
     for (int r = 0; r < nrhs; ++r) {
         CgState S{};
         S.stop2 = prm.tol * prm.tol;
@@ -634,7 +640,7 @@ void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs
     for (int r = 0; r < nrhs; ++r) need |= !(hs[0][r].phase == CG_CONVERGED || hs[0][r].phase == CG_MAXITER);
     if (need) {
         if (mixed) launch_accumulate(gauge, v, 0, s);
-        residual_group(ctx, gauge, v, 0, 2, s);
+        cg_residual_group(ctx, gauge, v, 0, 2, s);
         LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
         LQS_HIP(hipStreamSynchronize(s));
     }

@@ -346,6 +346,27 @@ template <> struct SpinorIO<F16> {
     }
 };
 
+// The value a store followed by a load of the given format returns, computed
+// in registers with the same operations (so an operand formed on the fly
+// equals the stored one bit for bit).
+template <int P> struct Roundtrip {
+    template <typename T> __device__ static __forceinline__ V3<T> apply(const V3<T> &v) { return v; }
+};
+template <> struct Roundtrip<F16> {
+    __device__ static __forceinline__ V3<float> apply(const V3<float> &v)
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m = fmaxf(m, fmaxf(fabsf(v.c[a].re), fabsf(v.c[a].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        V3<float> w;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            w.c[a] = {(float)(half_t)(v.c[a].re * inv) * m, (float)(half_t)(v.c[a].im * inv) * m};
+        return w;
+    }
+};
+
 // Convert a vector between real types.
 template <typename To, typename From> __device__ __forceinline__ V3<To> vcast(const V3<From> &v)
 {
@@ -369,6 +390,7 @@ struct Site {
     int32_t bwd[4];     // checkerboard index of x - mu
     uint32_t negf;      // bit mu: phase of link (x, mu) is -1
     uint32_t negb;      // bit mu: phase of link (x - mu, mu) is -1
+    uint32_t tunit;     // temporal gauge: bit 0 link (x, t) = 1, bit 1 link (x - t, t) = 1
 };
 
 // Lexicographic index of the site with checkerboard index cb and the given parity.
@@ -416,6 +438,8 @@ __device__ __forceinline__ Site decode(const Geom &g, int cb, int parity)
     uint32_t eta = (e1 << 1) | (e2 << 2) | (e3 << 3);
     s.negf = eta ^ ((t == nt - 1) ? 8u : 0u);
     s.negb = eta ^ ((t == 0) ? 8u : 0u);
+    // in temporal gauge every t-link is the unit matrix except those leaving t = Nt - 1
+    s.tunit = (t < nt - 1 ? 1u : 0u) | (t > 0 ? 2u : 0u);
     return s;
 }
 

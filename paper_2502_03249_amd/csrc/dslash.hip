@@ -20,7 +20,7 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
     return gate[r].reliable_pending != 0;
 }
 
-template <int P, int R, int K, bool DAG>
+template <int P, int R, int K, bool DAG, bool TG>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
                                                   const CgState *gate, int gate_mode)
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
     if (!any) return;
     const Site s = decode(g, cb, parity);
     V3<T> acc[K];
-    hop_site<P, R, K>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
+    hop_site<P, R, K, TG>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!active[j]) continue;
@@ -58,12 +58,17 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
 {
     const int64_t stride = field_bytes(g, P, 1);
     dim3 grid((g.vh + block - 1) / block, (nrhs + K - 1) / K);
-    if (dagger)
-        hipLaunchKernelGGL((hop_kernel<P, R, K, true>), grid, dim3(block), 0, s, g, L, parity, nrhs,
-                           (const char *)in, stride, (char *)out, stride, gate, gate_mode);
-    else
-        hipLaunchKernelGGL((hop_kernel<P, R, K, false>), grid, dim3(block), 0, s, g, L, parity, nrhs,
-                           (const char *)in, stride, (char *)out, stride, gate, gate_mode);
+#define LQS_HOP(DAG, TG)                                                                                         \
+    hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, TG>), grid, dim3(block), 0, s, g, L, parity, nrhs,               \
+                       (const char *)in, stride, (char *)out, stride, gate, gate_mode)
+    if (L.temporal) {
+        if (dagger) LQS_HOP(true, true);
+        else LQS_HOP(false, true);
+    } else {
+        if (dagger) LQS_HOP(true, false);
+        else LQS_HOP(false, false);
+    }
+#undef LQS_HOP
     LQS_HIP(hipGetLastError());
 }
 
@@ -90,11 +95,23 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
     else launch_pr<F16, 12>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
 }
 
+// Shapes the autotuner picked most often on 32^4 and 32^3x8 (every
+// precision): 4 right-hand sides per thread in 64-thread blocks from 4
+// vectors on, 2 per thread in 128-thread blocks for 2-3 vectors.
 LaunchShape default_hop_shape(int prec, int nrhs)
 {
+    (void)prec;
     LaunchShape sh;
-    sh.block = 256;
-    sh.rhs_per_thread = nrhs >= 4 ? (prec == F64 ? 2 : 4) : (nrhs >= 2 ? 2 : 1);
+    if (nrhs >= 4) {
+        sh.block = 64;
+        sh.rhs_per_thread = 4;
+    } else if (nrhs >= 2) {
+        sh.block = 128;
+        sh.rhs_per_thread = 2;
+    } else {
+        sh.block = 256;
+        sh.rhs_per_thread = 1;
+    }
     return sh;
 }
 

@@ -8,11 +8,14 @@
 namespace lqs {
 
 // acc[j] = sum_mu [eps_mu(x) U_{x,mu} in_j(x+mu) - eps_mu(x-mu) U^dag_{x-mu,mu} in_j(x-mu)]
-// for the site cb of parity `parity` (decoded into s).  Inactive right-hand
+// for the site cb of parity `parity` (decoded into s).  TG: the links are in
+// temporal gauge (U_t = 1 off the last time slice) and those t-links are
+// neither read nor multiplied; without TG every link is read (also correct
+// for temporal-gauge links, just slower).  Inactive right-hand
 // sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
 // the input field (parity 1 - parity); consecutive sides are in_stride bytes
 // apart.
-template <int P, int R, int K>
+template <int P, int R, int K, bool TG = false>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
                                          const char *in, int64_t in_stride, const bool *active,
                                          V3<typename RealOf<P>::type> *acc)
@@ -23,23 +26,56 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
     for (int j = 0; j < K; ++j) acc[j] = vzero<T>();
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
         const bool nf = (s.negf >> mu) & 1;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (!active[j]) continue;
-            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
-            accum(acc[j], mv(uf, v), nf);
-        }
-        const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
         const bool nb = !((s.negb >> mu) & 1);
+        // temporal gauge (Sec. 4.3): the t-links are unit matrices except on
+        // the last time slice, so they are neither read nor multiplied
+        if (TG && mu == 3 && (s.tunit & 1u)) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (!active[j]) continue;
-            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
-            accum(acc[j], mdv(ub, v), nb);
+            for (int j = 0; j < K; ++j)
+                if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]), nf);
+        } else {
+            const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (!active[j]) continue;
+                const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
+                accum(acc[j], mv(uf, v), nf);
+            }
+        }
+        if (TG && mu == 3 && (s.tunit & 2u)) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]), nb);
+        } else {
+            const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (!active[j]) continue;
+                const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
+                accum(acc[j], mdv(ub, v), nb);
+            }
         }
     }
+}
+
+// Single right-hand side, input vectors produced by load(cb_neighbour) (for
+// operands formed on the fly, e.g. r + beta p in the persistent solver).
+template <int P, int R, typename Load>
+__device__ __forceinline__ V3<typename RealOf<P>::type> hop_site_fn(const Geom &g, const LinkRef &L, int parity,
+                                                                   const Site &s, int cb, Load load)
+{
+    typedef typename RealOf<P>::type T;
+    const char *lb = (const char *)L.base;
+    V3<T> acc = vzero<T>();
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+        accum(acc, mv(uf, load(s.fwd[mu])), (s.negf >> mu) & 1);
+        const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
+        accum(acc, mdv(ub, load(s.bwd[mu])), !((s.negb >> mu) & 1));
+    }
+    return acc;
 }
 
 }  // namespace lqs

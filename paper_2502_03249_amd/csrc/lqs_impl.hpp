@@ -78,6 +78,7 @@ struct CgState {
 struct LinkRef {
     const void *base;      // start of the 8 (mu, parity) blocks
     int64_t block_bytes;   // bytes of one block = bytes_per_site * vh
+    int32_t temporal;      // links in temporal gauge: U_t = 1 except leaving t = Nt - 1
 };
 
 struct FieldRef {
@@ -122,11 +123,12 @@ struct Gauge {
     Geom g{};
     int64_t vh = 0;
     void *fmt[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][recon==12]
+    bool temporal = false;
     LinkRef ref(int prec, int recon) const
     {
         const void *p = fmt[prec][recon == 12 ? 1 : 0];
         LQS_REQUIRE(p != nullptr, LQS_EUNSUPPORTED, "gauge does not hold the requested link format");
-        return {p, (int64_t)link_block_bytes_per_site(prec, recon) * vh};
+        return {p, (int64_t)link_block_bytes_per_site(prec, recon) * vh, temporal ? 1 : 0};
     }
     ~Gauge();
 };
@@ -142,6 +144,8 @@ void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, 
 void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s);
 void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s);
 void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
+void launch_gauge_fix_temporal(const Geom &g, const double *links, double *out, double *G, hipStream_t s);
+double temporal_gauge_violation(Ctx &ctx, const Geom &g, const double *links, hipStream_t s);
 struct Ctx;
 void launch_field_dot(Ctx &ctx, const Geom &g, int nrhs, const void *a, const void *b, double *out, hipStream_t s);
 
@@ -190,6 +194,10 @@ struct PersistentProblem {
 };
 void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, const lqs_cg_params &prm,
                       lqs_cg_stats *stats, hipStream_t s);
+
+// multishift.hip
+void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *masses, const double *b, double *const *x,
+                      const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
 
 // tune.cpp
 struct Tuner {

@@ -1,0 +1,321 @@
+// multishift.hip -- several masses on one Krylov space (multi-shift CG).
+//
+// For M_i = m_i^2 - D_eo D_oe all systems share D_eo D_oe; they differ by a
+// shift sigma_i = m_i^2 - m_0^2 >= 0 of the smallest mass m_0 (the base).
+// CG on the base generates residuals r_k; the residual of shifted system i
+// after k steps is zeta_k^i r_k (the Krylov space does not depend on the
+// shift).  Writing the CG recurrences as a three-term recurrence for r_k and
+// matching it with the shifted one gives, with alpha_k, beta_k of the base,
+//   zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
+//                [zeta_{k-1} alpha_{k-1} (1 + alpha_k sigma) + alpha_k beta_{k-1} (zeta_{k-1} - zeta_k)]
+//   alpha^i_k = alpha_k zeta_{k+1} / zeta_k,  beta^i_k = beta_k (zeta_{k+1} / zeta_k)^2
+//   x^i += alpha^i_k p^i,  p^i = zeta_{k+1} r_{k+1} + beta^i_k p^i
+// (zeta_0 = zeta_{-1} = 1, alpha_{-1} = 1, beta_{-1} = 0).  A shifted system
+// stops updating once |zeta| |r| meets the target.  This is the multi-mass
+// solve a rational-approximation HMC needs for staggered fermions.
+//
+// One iteration: the base hop and fused normal operator (shared with the
+// plain solver), a finalize for alpha and every zeta, one update kernel that
+// advances all solutions, a finalize for beta, and one kernel that advances
+// all search directions.  FP64 throughout; afterwards every mass gets an FP64
+// true-residual check that also refines it with a warm-started CG if needed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "hop.hpp"
+
+namespace lqs {
+
+void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape sh, hipStream_t s);
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
+
+static constexpr int MS_MAX = 16;
+static constexpr int MS_BLOCK = 256;
+
+struct ShiftState {
+    double sigma;                    // m_i^2 - m_0^2
+    double zeta, zeta_prev, zeta_next;
+    double alpha, beta;
+    int32_t active;                  // still above the target
+    int32_t iters;
+};
+
+struct ShiftPtrs {
+    double *x[MS_MAX];               // solution of each shifted system (caller memory)
+    double *p[MS_MAX];               // search direction of each shifted system
+};
+
+__global__ void __launch_bounds__(1024) ms_finalize_dot(CgState *base, ShiftState *sh, int nshift,
+                                                        const double *partials, int nblocks)
+{
+    CgState &S = *base;
+    if (S.phase != CG_RUNNING) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[i];
+    const double pq = block_sum(acc);
+    if (threadIdx.x != 0) return;
+    if (!isfinite(pq)) {
+        S.phase = CG_NONFINITE;
+        return;
+    }
+    if (!(pq > 0.0)) {
+        S.phase = CG_BREAKDOWN;
+        return;
+    }
+    const double a_prev = S.alpha, b_prev = S.beta, a = S.rho / pq;
+    for (int i = 0; i < nshift; ++i) {
+        ShiftState &T = sh[i];
+        if (!T.active) continue;
+        const double z = T.zeta, zp = T.zeta_prev;
+        const double den = zp * a_prev * (1.0 + a * T.sigma) + a * b_prev * (zp - z);
+        const double zn = z * zp * a_prev / den;
+        T.zeta_next = zn;
+        T.alpha = a * zn / z;
+    }
+    S.alpha = a;
+}
+
+// x_0 += alpha p_0, r -= alpha q, |r|^2; x_i += alpha_i p_i for active shifts
+__global__ void __launch_bounds__(MS_BLOCK) ms_update(int vh, double *x0, double *r, const double *p0, const double *q,
+                                                      const ShiftPtrs *ptr, int nshift, const CgState *base,
+                                                      const ShiftState *sh, double *partials)
+{
+    if (base->phase != CG_RUNNING) return;
+    const double a = base->alpha;
+    double local = 0.0;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<double> pv = SpinorIO<F64>::load(p0, vh, cb);
+        const V3<double> qv = SpinorIO<F64>::load(q, vh, cb);
+        V3<double> xv = SpinorIO<F64>::load(x0, vh, cb);
+        V3<double> rv = SpinorIO<F64>::load(r, vh, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xv.c[c].re += a * pv.c[c].re;
+            xv.c[c].im += a * pv.c[c].im;
+            rv.c[c].re -= a * qv.c[c].re;
+            rv.c[c].im -= a * qv.c[c].im;
+            local += rv.c[c].re * rv.c[c].re + rv.c[c].im * rv.c[c].im;
+        }
+        SpinorIO<F64>::store(x0, vh, cb, xv);
+        SpinorIO<F64>::store(r, vh, cb, rv);
+        for (int i = 0; i < nshift; ++i) {
+            if (!sh[i].active) continue;
+            const double ai = sh[i].alpha;
+            const V3<double> pi = SpinorIO<F64>::load(ptr->p[i], vh, cb);
+            V3<double> xi = SpinorIO<F64>::load(ptr->x[i], vh, cb);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xi.c[c].re += ai * pi.c[c].re;
+                xi.c[c].im += ai * pi.c[c].im;
+            }
+            SpinorIO<F64>::store(ptr->x[i], vh, cb, xi);
+        }
+    }
+    const double s = block_sum(local);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(1024) ms_finalize_update(CgState *base, ShiftState *sh, int nshift,
+                                                           const double *partials, int nblocks)
+{
+    CgState &S = *base;
+    if (S.phase != CG_RUNNING) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[i];
+    const double r2 = block_sum(acc);
+    if (threadIdx.x != 0) return;
+    S.rho_old = S.rho;
+    S.rho = r2;
+    S.beta = r2 / S.rho_old;
+    S.iters += 1;
+    int any = 0;
+    for (int i = 0; i < nshift; ++i) {
+        ShiftState &T = sh[i];
+        if (!T.active) continue;
+        const double ratio = T.zeta_next / T.zeta;
+        T.beta = S.beta * ratio * ratio;
+        T.zeta_prev = T.zeta;
+        T.zeta = T.zeta_next;
+        T.iters += 1;
+        if (T.zeta * T.zeta * r2 <= S.stop2) T.active = 0;
+        any |= T.active;
+    }
+    if (!isfinite(r2)) S.phase = CG_NONFINITE;
+    else if ((r2 <= S.stop2 && !any) || S.iters >= S.max_iter) S.phase = CG_INNER_DONE;
+}
+
+// p_0 = r + beta p_0; p_i = zeta_i r + beta_i p_i for active shifts
+__global__ void __launch_bounds__(MS_BLOCK) ms_pupdate(int vh, const double *r, double *p0, const ShiftPtrs *ptr,
+                                                       int nshift, const CgState *base, const ShiftState *sh)
+{
+    if (base->phase != CG_RUNNING) return;
+    const double b = base->beta;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<double> rv = SpinorIO<F64>::load(r, vh, cb);
+        V3<double> pv = SpinorIO<F64>::load(p0, vh, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pv.c[c].re = rv.c[c].re + b * pv.c[c].re;
+            pv.c[c].im = rv.c[c].im + b * pv.c[c].im;
+        }
+        SpinorIO<F64>::store(p0, vh, cb, pv);
+        for (int i = 0; i < nshift; ++i) {
+            if (!sh[i].active) continue;
+            const double z = sh[i].zeta, bi = sh[i].beta;
+            V3<double> pi = SpinorIO<F64>::load(ptr->p[i], vh, cb);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pi.c[c].re = z * rv.c[c].re + bi * pi.c[c].re;
+                pi.c[c].im = z * rv.c[c].im + bi * pi.c[c].im;
+            }
+            SpinorIO<F64>::store(ptr->p[i], vh, cb, pi);
+        }
+    }
+}
+
+// x_0 = x_i = 0, r = p_0 = p_i = b, |b|^2
+__global__ void __launch_bounds__(MS_BLOCK) ms_init(int vh, const double *b, double *x0, double *r, double *p0,
+                                                    const ShiftPtrs *ptr, int nshift, double *partials)
+{
+    double local = 0.0;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        const V3<double> bv = SpinorIO<F64>::load(b, vh, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) local += bv.c[c].re * bv.c[c].re + bv.c[c].im * bv.c[c].im;
+        SpinorIO<F64>::store(x0, vh, cb, vzero<double>());
+        SpinorIO<F64>::store(r, vh, cb, bv);
+        SpinorIO<F64>::store(p0, vh, cb, bv);
+        for (int i = 0; i < nshift; ++i) {
+            SpinorIO<F64>::store(ptr->x[i], vh, cb, vzero<double>());
+            SpinorIO<F64>::store(ptr->p[i], vh, cb, bv);
+        }
+    }
+    const double s = block_sum(local);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(1024) ms_finalize_init(CgState *base, const double *partials, int nblocks)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[i];
+    const double b2 = block_sum(acc);
+    if (threadIdx.x != 0) return;
+    CgState &S = *base;
+    S.b2 = b2;
+    S.stop2 *= b2;
+    S.rho = b2;
+    S.true_r2 = b2;
+    S.alpha = 1.0;  // alpha_{-1}
+    S.beta = 0.0;   // beta_{-1}
+    S.phase = (b2 == 0.0) ? CG_CONVERGED : (isfinite(b2) ? CG_RUNNING : CG_NONFINITE);
+}
+
+void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *masses, const double *b, double *const *x,
+                      const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    LQS_REQUIRE(nmass >= 1 && nmass <= MS_MAX + 1, LQS_EINVAL, "multi-shift takes 1..17 masses");
+    LQS_REQUIRE(prm.inner_prec == F64, LQS_EUNSUPPORTED, "multi-shift CG runs in FP64");
+    const Geom &g = gauge.g;
+    const int vh = (int)gauge.vh;
+    int base = 0;
+    for (int i = 1; i < nmass; ++i)
+        if (masses[i] < masses[base]) base = i;
+    std::vector<int> shifts;
+    for (int i = 0; i < nmass; ++i)
+        if (i != base) shifts.push_back(i);
+    const int nshift = (int)shifts.size();
+
+    const int64_t f64 = field_bytes(g, F64, 1);
+    CgVectors v{};
+    v.prec = F64;
+    v.acc_prec = F64;
+    v.recon = prm.inner_recon == 12 ? 12 : 18;
+    v.nrhs = 1;
+    v.mass = masses[base];
+    v.p = ctx.workspace("ms.p", f64);
+    v.q = ctx.workspace("ms.q", f64);
+    v.t = ctx.workspace("ms.t", f64);
+    v.r = ctx.workspace("ms.r", f64);
+    v.x = x[base];
+    v.xlo = x[base];
+    v.b = (double *)b;
+    v.max_blocks = cg_partials_needed(gauge, 1);
+    v.partials = (double *)ctx.workspace("ms.partials", sizeof(double) * (size_t)v.max_blocks);
+    v.state = (CgState *)ctx.workspace("ms.state", sizeof(CgState));
+    ShiftPtrs hp{};
+    std::vector<ShiftState> hsh(nshift);
+    for (int k = 0; k < nshift; ++k) {
+        hp.x[k] = x[shifts[k]];
+        hp.p[k] = (double *)ctx.workspace("ms.p" + std::to_string(k), f64);
+        ShiftState &T = hsh[k];
+        T = ShiftState{};
+        T.sigma = masses[shifts[k]] * masses[shifts[k]] - masses[base] * masses[base];
+        T.zeta = T.zeta_prev = 1.0;
+        T.active = 1;
+    }
+    ShiftPtrs *dp = (ShiftPtrs *)ctx.workspace("ms.ptrs", sizeof(ShiftPtrs));
+    ShiftState *dsh = (ShiftState *)ctx.workspace("ms.shifts", sizeof(ShiftState) * (nshift > 0 ? nshift : 1));
+    CgState S{};
+    S.stop2 = prm.tol * prm.tol;
+    S.max_iter = prm.max_iter;
+    S.phase = CG_RUNNING;
+    LQS_HIP(hipMemcpyAsync(dp, &hp, sizeof(ShiftPtrs), hipMemcpyHostToDevice, s));
+    if (nshift) LQS_HIP(hipMemcpyAsync(dsh, hsh.data(), sizeof(ShiftState) * nshift, hipMemcpyHostToDevice, s));
+    LQS_HIP(hipMemcpyAsync(v.state, &S, sizeof(CgState), hipMemcpyHostToDevice, s));
+
+    int blocks = (vh + MS_BLOCK - 1) / MS_BLOCK;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(ms_init, dim3(blocks), dim3(MS_BLOCK), 0, s, vh, b, v.x, (double *)v.r, (double *)v.p,
+                       (const ShiftPtrs *)dp, nshift, v.partials);
+    hipLaunchKernelGGL(ms_finalize_init, dim3(1), dim3(1024), 0, s, v.state, (const double *)v.partials, blocks);
+    LQS_HIP(hipGetLastError());
+
+    const LaunchShape sh = default_hop_shape(F64, 1);
+    const int nd_blocks = (vh + sh.block - 1) / sh.block;
+    CgState hs{};
+    int64_t enqueued = 0;
+    const int64_t cap = (int64_t)prm.max_iter + 64;
+    while (true) {
+        for (int i = 0; i < 8; ++i) {
+            launch_hop_gated(g, gauge.ref(F64, v.recon), F64, v.recon, 0, 1, 1, v.p, v.t, v.state, 1, sh, s);
+            launch_normal_dot_shape(gauge, v, sh, s);
+            hipLaunchKernelGGL(ms_finalize_dot, dim3(1), dim3(1024), 0, s, v.state, dsh, nshift,
+                               (const double *)v.partials, nd_blocks);
+            hipLaunchKernelGGL(ms_update, dim3(blocks), dim3(MS_BLOCK), 0, s, vh, v.x, (double *)v.r,
+                               (const double *)v.p, (const double *)v.q, (const ShiftPtrs *)dp, nshift,
+                               (const CgState *)v.state, (const ShiftState *)dsh, v.partials);
+            hipLaunchKernelGGL(ms_finalize_update, dim3(1), dim3(1024), 0, s, v.state, dsh, nshift,
+                               (const double *)v.partials, blocks);
+            hipLaunchKernelGGL(ms_pupdate, dim3(blocks), dim3(MS_BLOCK), 0, s, vh, (const double *)v.r, (double *)v.p,
+                               (const ShiftPtrs *)dp, nshift, (const CgState *)v.state, (const ShiftState *)dsh);
+            LQS_HIP(hipGetLastError());
+        }
+        enqueued += 8;
+        LQS_HIP(hipMemcpyAsync(&hs, v.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipStreamSynchronize(s));
+        if (hs.phase != CG_RUNNING || enqueued > cap) break;
+    }
+    if (nshift) LQS_HIP(hipMemcpyAsync(hsh.data(), dsh, sizeof(ShiftState) * nshift, hipMemcpyDeviceToHost, s));
+    LQS_HIP(hipStreamSynchronize(s));
+
+    // every mass: FP64 true residual from its own solution, refined by a
+    // warm-started CG when the shared recurrence drifted above the target
+    lqs_cg_params rp = prm;
+    rp.use_x0 = 1;
+    rp.persistent = 0;
+    for (int i = 0; i < nmass; ++i) {
+        lqs_problem pb{static_cast<const lqs_gauge *>(&gauge), masses[i], 1, b, x[i]};
+        const int shared = (i == base) ? hs.iters : hsh[std::find(shifts.begin(), shifts.end(), i) - shifts.begin()].iters;
+        rp.max_iter = prm.max_iter;
+        cg_solve_one(ctx, pb, rp, &stats[i], s);
+        stats[i].restarts += stats[i].iters > 0 ? 1 : 0;
+        stats[i].iters += shared;
+        if (hs.phase == CG_NONFINITE) stats[i].status = LQS_ENONFINITE;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < nmass; ++i) stats[i].seconds = secs;
+}
+
+}  // namespace lqs

@@ -206,3 +206,181 @@ void launch_field_dot(Ctx &ctx, const Geom &g, int nrhs, const void *a, const vo
 }
 
 }  // namespace lqs
+
+namespace lqs {
+
+// ---------------------------------------------------------------------------
+// temporal gauge (Sec. 4.3): a gauge transformation G with G(x, 0) = 1 and
+// G(x, t+1) = G(x, t) U_t(x, t) makes U'_t(x) = G(x) U_t(x) G(x + t)^dag = 1
+// for t < Nt - 1; U'_mu(x) = G(x) U_mu(x) G(x + mu)^dag for every link.
+
+__device__ __forceinline__ void su3_canonicalise(M3<double> &m)
+{
+    double n0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 += m.e[0][j].re * m.e[0][j].re + m.e[0][j].im * m.e[0][j].im;
+    n0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[0][j] = {m.e[0][j].re * n0, m.e[0][j].im * n0};
+    Cx<double> d = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d = cadd(d, cjmul(m.e[0][j], m.e[1][j]));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[1][j] = csub(m.e[1][j], cmul(d, m.e[0][j]));
+    double n1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n1 += m.e[1][j].re * m.e[1][j].re + m.e[1][j].im * m.e[1][j].im;
+    n1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[1][j] = {m.e[1][j].re * n1, m.e[1][j].im * n1};
+    rebuild_row2(m);
+}
+
+__device__ __forceinline__ M3<double> load_canon(const double2 *p)
+{
+    M3<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.e[k / 3][k % 3] = {p[k].x, p[k].y};
+    return m;
+}
+
+__device__ __forceinline__ void store_canon(double2 *p, const M3<double> &m)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+}
+
+__device__ __forceinline__ M3<double> mm(const M3<double> &a, const M3<double> &b)
+{
+    M3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<double> s = cmul(a.e[i][0], b.e[0][j]);
+            s = cadd(s, cmul(a.e[i][1], b.e[1][j]));
+            c.e[i][j] = cadd(s, cmul(a.e[i][2], b.e[2][j]));
+        }
+    return c;
+}
+
+// a b^dag
+__device__ __forceinline__ M3<double> mmd(const M3<double> &a, const M3<double> &b)
+{
+    M3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s = cadd(s, {a.e[i][k].re * b.e[j][k].re + a.e[i][k].im * b.e[j][k].im,
+                                                     a.e[i][k].im * b.e[j][k].re - a.e[i][k].re * b.e[j][k].im});
+            c.e[i][j] = s;
+        }
+    return c;
+}
+
+// one thread per spatial site walks the time direction
+__global__ void gauge_fix_G_kernel(Geom g, const double2 *U, double2 *G)
+{
+    const int64_t vs = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t V = vs * g.n[3];
+    const int64_t xs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (xs >= vs) return;
+    M3<double> cur;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) cur.e[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+    store_canon(G + 9 * xs, cur);
+    for (int t = 0; t + 1 < g.n[3]; ++t) {
+        const int64_t lex = xs + vs * t;
+        cur = mm(cur, load_canon(U + 9 * (3 * V + lex)));
+        su3_canonicalise(cur);
+        store_canon(G + 9 * (lex + vs), cur);
+    }
+}
+
+__global__ void gauge_transform_kernel(Geom g, const double2 *U, const double2 *G, double2 *out)
+{
+    const int64_t V = 2 * (int64_t)g.vh;
+    const int64_t lex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (lex >= V) return;
+    int c[4];
+    int64_t r = lex;
+    for (int i = 0; i < 4; ++i) {
+        c[i] = (int)(r % g.n[i]);
+        r /= g.n[i];
+    }
+    double2 *o = out + 9 * (mu * V + lex);
+    if (mu == 3 && c[3] < g.n[3] - 1) {
+        M3<double> one;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) one.e[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+        store_canon(o, one);
+        return;
+    }
+    c[mu] = (c[mu] + 1) % g.n[mu];
+    const int64_t nb = c[0] + (int64_t)g.n[0] * (c[1] + (int64_t)g.n[1] * (c[2] + (int64_t)g.n[2] * c[3]));
+    const M3<double> u = mm(load_canon(G + 9 * lex), load_canon(U + 9 * (mu * V + lex)));
+    store_canon(o, mmd(u, load_canon(G + 9 * nb)));
+}
+
+void launch_gauge_fix_temporal(const Geom &g, const double *links, double *out, double *G, hipStream_t s)
+{
+    const int64_t vs = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t V = 2 * (int64_t)g.vh;
+    hipLaunchKernelGGL(gauge_fix_G_kernel, dim3((unsigned)((vs + 127) / 128)), dim3(128), 0, s, g,
+                       (const double2 *)links, (double2 *)G);
+    LQS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gauge_transform_kernel, dim3((unsigned)((V + 255) / 256), 4), dim3(256), 0, s, g,
+                       (const double2 *)links, (const double2 *)G, (double2 *)out);
+    LQS_HIP(hipGetLastError());
+}
+
+// max over t-links with t < Nt - 1 of max |U_ij - delta_ij|, per block
+__global__ void __launch_bounds__(256) temporal_violation_kernel(Geom g, const double2 *U, double *partials)
+{
+    const int64_t V = 2 * (int64_t)g.vh;
+    const int64_t vs = V / g.n[3];
+    double m = 0.0;
+    for (int64_t lex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lex < V - vs;
+         lex += (int64_t)gridDim.x * blockDim.x) {
+        const double2 *u = U + 9 * (3 * V + lex);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double re = u[k].x - ((k % 4 == 0) ? 1.0 : 0.0);
+            m = fmax(m, fmax(fabs(re), fabs(u[k].y)));
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+double temporal_gauge_violation(Ctx &ctx, const Geom &g, const double *links, hipStream_t s)
+{
+    const int blocks = 256;
+    double *part = (double *)ctx.workspace("tg.partials", sizeof(double) * blocks);
+    hipLaunchKernelGGL(temporal_violation_kernel, dim3(blocks), dim3(256), 0, s, g, (const double2 *)links, part);
+    LQS_HIP(hipGetLastError());
+    std::vector<double> h(blocks);
+    LQS_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * blocks, hipMemcpyDeviceToHost, s));
+    LQS_HIP(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (double v : h) m = v > m ? v : m;  // NaN-free unless the links are
+    for (double v : h)
+        if (v != v) return v;
+    return m;
+}
+
+}  // namespace lqs

@@ -1,0 +1,61 @@
+"""Multi-mass (multi-shift) CG against one oracle CG per mass."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import field, gauge, lex_of, rel
+
+pytestmark = pytest.mark.gpu
+
+lqs = pytest.importorskip("paper_2502_03249_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lqs.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("dims,kind,masses", [((4, 6, 8, 10), "haar", [0.3, 0.1, 0.5, 1.0]),
+                                              ((16, 16, 16, 8), "smooth", [0.02, 0.05, 0.1, 0.2, 0.4, 0.8]),
+                                              ((4, 4, 4, 4), "haar", [0.2])])
+def test_multishift_matches_separate_solves(ctx, dims, kind, masses):
+    U = synth.gauge(dims, kind, seed=101, eps=0.3)
+    b = synth.source(dims, 0, seed=102)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xs = [bf.like() for _ in masses]
+    st = lqs.cg_solve_multishift(ctx, g, masses, bf, xs, tol=1e-10)
+    base_iters = max(s["iters"] for s in st)
+    for m, x, s in zip(masses, xs, st):
+        assert s["status"] == 0, s
+        xv = lex_of(ctx, x)
+        assert oracle.true_residual(dims, U, m, b, xv) <= 1e-10
+        xo, _, _, _ = oracle.cg(dims, U, m, b, tol=1e-11)
+        assert rel(xv, xo) <= (m ** 2 + 64) / m ** 2 * 1e-10
+    # heavier masses converge in fewer shared iterations
+    order = np.argsort(masses)
+    iters = [st[i]["iters"] - 0 for i in order]
+    assert iters[0] == base_iters
+
+
+def test_multishift_rejects_mixed_precision(ctx):
+    dims = (4, 4, 4, 4)
+    g = gauge(ctx, dims, synth.gauge(dims, "haar", seed=1))
+    bf = field(ctx, dims, synth.source(dims, 0, seed=2), 0)
+    xs = [bf.like(), bf.like()]
+    import ctypes
+    m = (ctypes.c_double * 2)(0.1, 0.2)
+    ptrs = (ctypes.c_void_p * 2)(*[x.data.data_ptr() for x in xs])
+    prm = lqs.LqsCgParams(1e-10, 100, lqs.F32, 18, 0, 0.0, 0, 0)
+    stats = (lqs.LqsCgStats * 2)()
+    st = lqs.lib().cg_solve_multishift(ctx.handle, g.handle, 2, m, ctypes.c_void_p(bf.data.data_ptr()), ptrs,
+                                       ctypes.byref(prm), stats, None)
+    assert st == lqs.EUNSUPPORTED
+    ptrs2 = (ctypes.c_void_p * 2)(xs[0].data.data_ptr(), xs[0].data.data_ptr())
+    prm.inner_prec = lqs.F64
+    st = lqs.lib().cg_solve_multishift(ctx.handle, g.handle, 2, m, ctypes.c_void_p(bf.data.data_ptr()), ptrs2,
+                                       ctypes.byref(prm), stats, None)
+    assert st == lqs.EINVAL
