@@ -1,10 +1,12 @@
 """CPU FP64 oracle for the staggered even-odd solver -- TEST INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
-import this package.  It wraps ``oracle.c`` (plain C, FP64, OpenMP over sites
-in the operator, serial reductions) through ctypes and shares nothing with the
-GPU library.  Conventions and the definition of every function are documented
-in ``oracle.c``.
+import this package.  It wraps ``oracle.c`` (the operator, CG and fermion
+derivative) and ``hmc.c`` (plaquette action and derivative, SU(3)
+exponential, pseudofermion heat bath, one HMC trajectory) -- plain C, FP64,
+OpenMP over sites in the operator, serial reductions -- through ctypes and
+shares nothing with the GPU library.  Conventions and the definition of every
+function are documented in the C sources.
 
 Arrays are numpy complex128: links (4, Nt, Nz, Ny, Nx, 3, 3), colour-vector
 fields (Nt, Nz, Ny, Nx, 3) on the full lattice, with zeros off the parity a
@@ -17,14 +19,14 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hmc.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build():
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-o", _LIB + ".tmp"] + _SRCS + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
 
@@ -54,6 +56,20 @@ def load():
     lib.ora_force.restype = None
     lib.ora_threads.argtypes = []
     lib.ora_threads.restype = i32
+    lib.ora_expm3.argtypes = [vp, vp]
+    lib.ora_expm3.restype = None
+    lib.ora_plaquette_action.argtypes = [i32p, vp, d]
+    lib.ora_plaquette_action.restype = d
+    lib.ora_gauge_force.argtypes = [i32p, vp, d, d, vp]
+    lib.ora_gauge_force.restype = None
+    lib.ora_kinetic.argtypes = [i32p, vp]
+    lib.ora_kinetic.restype = d
+    lib.ora_pseudofermion.argtypes = [i32p, vp, d, vp, vp]
+    lib.ora_pseudofermion.restype = None
+    lib.ora_link_update.argtypes = [i32p, vp, vp, d]
+    lib.ora_link_update.restype = None
+    lib.ora_hmc.argtypes = [i32p, vp, vp, vp, d, d, d, i32, i32, d, i32, d, d, vp, vp, vp, i32p, i32p, i32p, vp]
+    lib.ora_hmc.restype = i32
     _lib = lib
     return lib
 
@@ -137,3 +153,79 @@ def force(dims, U, X, Y=None, coeff=1.0, mode=0):
 
 def threads():
     return int(load().ora_threads())
+
+
+OMELYAN_LAMBDA = 0.1931833275037836
+
+
+def expm3(A):
+    """exp(A) of one 3x3 complex matrix (scaling and squaring of the Taylor series)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    assert A.shape == (3, 3)
+    out = np.empty_like(A)
+    load().ora_expm3(A.ctypes.data, out.ctypes.data)
+    return out
+
+
+def plaquette_action(dims, U, beta):
+    """S_g = beta sum_x sum_{mu<nu} (1 - Re tr P_{mu nu}(x) / 3)."""
+    d, dp = _dims(dims)
+    U = _links(U, d)
+    return float(load().ora_plaquette_action(dp, U.ctypes.data, float(beta)))
+
+
+def gauge_force(dims, U, beta, coeff=1.0):
+    """coeff * F_g, F_g = (beta/3) TA(U V) with V the staple sum of each link."""
+    d, dp = _dims(dims)
+    U = _links(U, d)
+    out = np.empty_like(U)
+    load().ora_gauge_force(dp, U.ctypes.data, float(beta), float(coeff), out.ctypes.data)
+    return out
+
+
+def kinetic(dims, Q):
+    """K = -sum_links tr(Q^2)."""
+    d, dp = _dims(dims)
+    Q = _links(Q, d)
+    return float(load().ora_kinetic(dp, Q.ctypes.data))
+
+
+def pseudofermion(dims, U, mass, eta):
+    """phi = m eta_e - D_eo eta_o on even sites."""
+    d, dp = _dims(dims)
+    U, eta = _links(U, d), _field(eta, d)
+    out = np.empty_like(eta)
+    load().ora_pseudofermion(dp, U.ctypes.data, float(mass), eta.ctypes.data, out.ctypes.data)
+    return out
+
+
+def link_update(dims, U, Q, eps):
+    """exp(eps Q) U on every link (returns a new array)."""
+    d, dp = _dims(dims)
+    U = _links(U, d).copy()
+    Q = _links(Q, d)
+    load().ora_link_update(dp, U.ctypes.data, Q.ctypes.data, float(eps))
+    return U
+
+
+def hmc(dims, U, Q, eta, mass, beta, tau, nsteps, integrator="leapfrog", lam=OMELYAN_LAMBDA, fermions=True,
+        cg_tol=1e-12, u=0.5, phi=None):
+    """One HMC trajectory.  The pseudofermion is made from the Gaussians eta on U, or given as phi
+    (then eta is ignored).  Returns a dict with the proposal U1, Q1, the pseudofermion phi, the
+    energies (K0, Sg0, Sf0, K1, Sg1, Sf1), dH, accepted, cg_iters, cg_solves, status."""
+    d, dp = _dims(dims)
+    U, Q = _links(U, d), _links(Q, d)
+    zero = np.zeros((d[3], d[2], d[1], d[0], 3), np.complex128)
+    mode = 0 if not fermions else (2 if phi is not None else 1)
+    pf = _field(phi if phi is not None else (eta if eta is not None else zero), d)
+    U1, Q1, phi_out = np.empty_like(U), np.empty_like(Q), np.empty_like(zero)
+    en = np.zeros(6)
+    acc, it, ns = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    integ = {"leapfrog": 0, "omelyan": 1}[integrator]
+    st = load().ora_hmc(dp, U.ctypes.data, Q.ctypes.data, pf.ctypes.data, float(mass), float(beta), float(tau),
+                        int(nsteps), integ, float(lam), mode, float(cg_tol), float(u), U1.ctypes.data,
+                        Q1.ctypes.data, en.ctypes.data, ctypes.byref(acc), ctypes.byref(it), ctypes.byref(ns),
+                        phi_out.ctypes.data)
+    dh = (en[3] + en[4] + en[5]) - (en[0] + en[1] + en[2])
+    return {"U1": U1, "Q1": Q1, "phi": phi_out, "energies": en, "dH": float(dh), "accepted": bool(acc.value),
+            "cg_iters": int(it.value), "cg_solves": int(ns.value), "status": int(st)}

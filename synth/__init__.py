@@ -39,7 +39,8 @@ def load():
     lib.synth_site_haar.argtypes = [i32p, ctypes.c_uint64, dp]
     lib.synth_gauge_algebra.argtypes = [i32p, ctypes.c_uint64, dp]
     lib.synth_source.argtypes = [i32p, ctypes.c_int32, ctypes.c_uint64, dp]
-    for f in (lib.synth_gauge, lib.synth_site_haar, lib.synth_gauge_algebra, lib.synth_source):
+    lib.synth_momenta.argtypes = [i32p, ctypes.c_uint64, dp]
+    for f in (lib.synth_gauge, lib.synth_site_haar, lib.synth_gauge_algebra, lib.synth_source, lib.synth_momenta):
         f.restype = None
     _lib = lib
     return lib
@@ -81,4 +82,12 @@ def source(dims, parity=0, seed=0):
     d, dp = _dims(dims)
     out = np.empty((d[3], d[2], d[1], d[0], 3), np.complex128)
     load().synth_source(dp, int(parity), int(seed), out.ctypes.data)
+    return out
+
+
+def momenta(dims, seed=0):
+    """Anti-Hermitian traceless Q = sum_a q_a (i lambda_a / 2), q_a ~ N(0,1); same shape as gauge()."""
+    d, dp = _dims(dims)
+    out = np.empty((4, d[3], d[2], d[1], d[0], 3, 3), np.complex128)
+    load().synth_momenta(dp, int(seed), out.ctypes.data)
     return out

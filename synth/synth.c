@@ -201,6 +201,39 @@ void synth_gauge_algebra(const int32_t dims[4], uint64_t seed, double *out)
 }
 
 /*
+ * Random su(3) momenta: Q = sum_a q_a T_a with T_a = i lambda_a / 2 (Gell-Mann
+ * lambda_a) and eight independent N(0,1) coefficients q_a per link, i.e.
+ * density ~ exp(tr Q^2).  Stream key = link index mu * V + lex.
+ */
+void synth_momenta(const int32_t dims[4], uint64_t seed, double *out)
+{
+    const long vol = (long)dims[0] * dims[1] * dims[2] * dims[3];
+    cplx *q = (cplx *)out;
+    const double r3 = 1.0 / sqrt(3.0);
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < 4 * vol; ++l) {
+        double a[8];
+        for (int k = 0; k < 4; ++k) {
+            cplx g = cgauss(seed, (uint64_t)l, (uint64_t)k);
+            a[2 * k] = creal(g);
+            a[2 * k + 1] = cimag(g);
+        }
+        /* H = sum_a q_a lambda_a / 2 (Hermitian traceless), Q = i H */
+        cplx h[9];
+        h[0] = 0.5 * (a[2] + a[7] * r3);
+        h[4] = 0.5 * (-a[2] + a[7] * r3);
+        h[8] = -a[7] * r3;
+        h[1] = 0.5 * (a[0] - I * a[1]);
+        h[2] = 0.5 * (a[3] - I * a[4]);
+        h[5] = 0.5 * (a[5] - I * a[6]);
+        h[3] = conj(h[1]);
+        h[6] = conj(h[2]);
+        h[7] = conj(h[5]);
+        for (int i = 0; i < 9; ++i) q[9 * l + i] = I * h[i];
+    }
+}
+
+/*
  * Complex Gaussian colour vectors, N(0,1) real and imaginary parts.
  * parity 0 or 1 fills only sites with (x+y+z+t) of that parity and leaves the
  * others zero; parity -1 fills every site.  Stream key = lex.
