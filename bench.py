@@ -16,7 +16,10 @@ in every link format (GB/s, GFLOP/s, fraction of 8 TB/s), and the CPU oracle.
 
 The hop kernels are timed with HIP events recorded on the stream they are
 launched on, inside the timed region; `roofline` reports the dominant kernel
-of the step.  Options --only-hop / --only-copy run the launches a rocprofv3
+of the step with the algorithmic bytes per launch (links, each input vector
+once, the output), and beside them the paper's model bytes (every neighbour
+read counted, Sec. 4.3) and the HBM traffic rocprofv3 measured on the same
+kernel source.  Options --only-hop / --only-copy run the launches a rocprofv3
 counter pass needs and nothing else.
 """
 import argparse
@@ -140,7 +143,9 @@ def main():
         n, ms, sites = lqs.profile_hops_result(ctx, pr, recon)
         lqs.profile_hops(ctx, False)
         mb = model.hop_model_bytes(pr, recon) * vh
-        return {"prec": prec, "recon": recon, "ms": ms, "model_GBps": mb / ms / 1e6,
+        nb = model.hop_min_bytes(pr, recon) * vh
+        return {"prec": prec, "recon": recon, "ms": ms, "model_GBps": mb / ms / 1e6, "min_GBps": nb / ms / 1e6,
+                "frac_hbm_min": nb / ms / 1e6 / PEAK_HBM_GBPS,
                 "GFLOPs": model.FLOPS_PER_SITE * vh / ms / 1e6, "frac_hbm": mb / ms / 1e6 / PEAK_HBM_GBPS,
                 "model_bytes_per_site": model.hop_model_bytes(pr, recon),
                 "min_bytes_per_site": model.hop_min_bytes(pr, recon), "launches": n}
@@ -199,15 +204,20 @@ def main():
     # standalone hop in every format
     hops = [hop_rate(p, r, a.hop_reps) for p in ("f64", "f32", "f16") for r in (18, 12)]
 
-    # roofline of the dominant kernel of the step: the inner-precision hop
+    # roofline of the dominant kernel of the step: the inner-precision hop.  achieved counts the
+    # algorithmic (minimum) bytes: links, each input vector once, the output; the paper's model
+    # bytes (every neighbour read counted) are reported beside it.
+    min_site = model.hop_min_bytes(inner, a.recon)
     mb_site = model.hop_model_bytes(inner, a.recon)
-    achieved = mb_site * vh / hop_ms / 1e6
+    achieved = min_site * vh / hop_ms / 1e6
     key = f"hop_{a.inner}_{a.recon}"
     traffic = traffic_for(key, vh)
     roof = {"bound": "hbm", "kernel": key, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
-            "bytes_per_launch": mb_site * vh, "avg_launch_ms": round(hop_ms, 5), "launches_timed": n_hop,
-            "working_launches": working}
+            "bytes_per_launch": min_site * vh, "bytes_per_site": min_site, "avg_launch_ms": round(hop_ms, 5),
+            "launches_timed": n_hop, "working_launches": working,
+            "model_bytes_per_site": mb_site, "model_GBps": round(mb_site * vh / hop_ms / 1e6, 1),
+            "traffic_GBps": round(traffic / hop_ms / 1e6, 1) if traffic else None}
     h64 = [h for h in hops if h["prec"] == "f64" and h["recon"] == 18][0]
 
     cpu = None
@@ -260,7 +270,7 @@ def run_suite(a):
     hop size sweep (Fig. 3 analogue) | multi-vector hop on 32^4 and 32^3x8 (Table 2
     analogue), default and autotuned shapes | 16-RHS block CG vs 16 single solves |
     uneven three-lattice batch, persistent vs separate | 4^4 and 32^3x8 FP64 CG |
-    24^4 action, adjoint and force.
+    24^4 action, adjoint and force | 24^4 plaquette force and HMC trajectories.
     """
     import numpy as np
     import torch
@@ -410,15 +420,26 @@ def run_suite(a):
         pr = lqs.PREC[prec]
         st = []
         ctx.set_tuning(tuned)
+        # one untimed call first: it runs the shape search when tuning is on
+        lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL, inner_prec=pr,
+                     reliable_interval=100, persistent=True)
         tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
                                                   tol=TOL, inner_prec=pr, reliable_interval=100,
                                                   persistent=True)), 3)
         ctx.set_tuning(False)
+        # one call, multi-kernel: the lattices run concurrently on side streams
         ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
                                         inner_prec=pr, reliable_interval=100), 3)
+
+        def sequential():
+            for g_, m_, b_, x_ in probs:
+                lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_())], tol=TOL, inner_prec=pr, reliable_interval=100)
+        tq = timed(sequential, 3)
         emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
-              "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5), "separate_s": round(ts, 5),
-              "speedup": round(ts / tp, 2), "iters": [r["iters"] for r in st[-1]],
+              "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5),
+              "concurrent_multikernel_s": round(ts, 5), "sequential_s": round(tq, 5),
+              "persistent_vs_sequential": round(tq / tp, 2), "concurrent_vs_sequential": round(tq / ts, 2),
+              "iters": [r["iters"] for r in st[-1]],
               "true_res": [r["true_rel_residual"] for r in st[-1]],
               "all_converged": all(r["status"] == 0 for r in st[-1])})
     for g_, _, _, _ in probs:
@@ -474,6 +495,39 @@ def run_suite(a):
     ms = event_ms(lambda: lqs.fermion_force(ctx, g, X, None, 1.0, 0, out), 10)
     emit({"suite": "force_24x4", "action_forward_backward_s": round(t, 4), "fermion_force_call_ms": round(ms, 4),
           "note": "fermion_force = one D_oe hop + the outer-product/projection kernel"})
+    del g, X, out
+
+    # 8. HMC on 24^4 (beta 5.5, m 0.05, tau 1): the plaquette force kernel alone, and whole
+    #    trajectories with FP64 and mixed-precision solves (warm-started), Omelyan, 10 steps
+    Ud = torch.from_numpy(synth.gauge(dims, "smooth", seed=1004, eps=0.2)).to(dev)
+    Qd = torch.from_numpy(synth.momenta(dims, seed=3005)).to(dev)
+    vol = int(np.prod(dims))
+    Fd = torch.empty_like(Qd)
+    ms = event_ms(lambda: lqs.gauge_force(ctx, dims, Ud, 5.5, 1.0, out=Fd, accumulate=True), 10)
+    links = 4 * vol
+    # minimum traffic: every link read once, the momentum read and written (144 B each)
+    emit({"suite": "gauge_force_24x4", "ms": round(ms, 4), "links": links,
+          "min_GBps": round(links * 3 * 144 / ms / 1e6, 1),
+          "GFLOPs_fp64": round(links * (25 * 198 + 60) / ms / 1e6, 1),
+          "note": "per link 24 SU(3) products for the 6 staples + U V (198 flop each) + TA"})
+    eta = torch.from_numpy(synth.source(dims, -1, seed=3006) / np.sqrt(2)).to(dev)
+    for inner, recon in (("f64", 18), ("f32", 12), ("f16", 12)):
+        res = []
+        for k in range(2):
+            U0 = Ud.clone()
+            Q0 = torch.from_numpy(synth.momenta(dims, seed=3010 + k)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lqs.hmc_trajectory(ctx, dims, U0, Q0, eta, u=0.5, beta=5.5, mass=0.05, tau=1.0, nsteps=10,
+                                    integrator=lqs.OMELYAN, fermions=1, tol=1e-10, inner_prec=lqs.PREC[inner],
+                                    inner_recon=recon, use_x0=True)
+            torch.cuda.synchronize()
+            res.append((time.perf_counter() - t0, st))
+        t_, st = res[-1]
+        emit({"suite": "hmc_24x4", "inner": inner, "recon": recon, "s_per_trajectory": round(t_, 4),
+              "cg_solves": st["cg_solves"], "cg_iters": st["cg_iters"], "dH": st["dH"],
+              "plaquette": st["plaquette"], "status": st["status"],
+              "note": "Omelyan, 10 steps, tau 1, beta 5.5, m 0.05, solves to 1e-10 warm-started"})
 
 
 if __name__ == "__main__":

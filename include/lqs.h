@@ -230,9 +230,91 @@ lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, 
  * TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6, the su(3) force with
  * dL/dw = Re tr(F^dag A) for U -> exp(w A) U; mode 1 writes coeff * Pi^dag,
  * the gradient with respect to the real and imaginary parts of each link
- * entry.  X, Y: FP64 native even fields (nrhs 1); force: canonical link layout. */
+ * entry; mode 2 adds coeff * (-TA(U Pi)) to force (a momentum update).
+ * X, Y: FP64 native even fields (nrhs 1); force: canonical link layout. */
 lqs_status fermion_force(lqs_ctx *ctx, const lqs_gauge *g, const double *X, const double *Y, double coeff,
                          int32_t mode, double *force, void *stream);
+
+/* ---- hybrid Monte Carlo ------------------------------------------------ */
+/* The simulation layer around the solver (Sec. 3 names HMC, the gauge action
+ * and its derivatives; the paper states no formulas, the definitions are the
+ * standard ones, fixed here).  Links and momenta use the canonical link
+ * layout (complex128 [4][Nt][Nz][Ny][Nx][3][3]); links are periodic in every
+ * direction (the antiperiodic t sign belongs to the fermion operator).
+ *   plaquette  P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+ *   S_g = beta sum_x sum_{mu<nu} (1 - Re tr P_{mu nu}(x) / 3)
+ *   momenta Q: anti-Hermitian traceless, K = -sum_links tr Q^2
+ *   force convention: F with dS/dw = Re tr(F^dag A) for U -> exp(w A) U;
+ *   the flow is dU/dtau = Q U, dQ/dtau = -F/2, which conserves
+ *   H = K + S_g + S_f, S_f = phi^dag M^-1 phi (M as in cg_solve). */
+
+/* *S = S_g of the links (FP64, fixed-order sum).  Synchronous on stream. */
+lqs_status gauge_action(lqs_ctx *ctx, const int32_t dims[4], const double *links, double beta, double *S,
+                        void *stream);
+
+/* out = coeff * F_g (accumulate = 0) or out += coeff * F_g (accumulate = 1),
+ * F_g = (beta/3) TA(U V) with V the sum of the six staples of each link, so
+ * that Re tr(U V) collects the plaquettes containing U.  out: canonical
+ * link layout; must not overlap links. */
+lqs_status gauge_force(lqs_ctx *ctx, const int32_t dims[4], const double *links, double beta, double coeff,
+                       int32_t accumulate, double *out, void *stream);
+
+/* links = exp(eps Q) links on every link (in place); Q: canonical layout,
+ * must not overlap links. */
+lqs_status link_update(lqs_ctx *ctx, const int32_t dims[4], double *links, const double *mom, double eps,
+                       void *stream);
+
+/* *K = -sum_links tr(Q^2).  Synchronous on stream. */
+lqs_status kinetic_energy(lqs_ctx *ctx, const int32_t dims[4], const double *mom, double *K, void *stream);
+
+enum { LQS_LEAPFROG = 0, LQS_OMELYAN = 1 };
+
+typedef struct {
+    double beta;        /* Wilson gauge coupling, >= 0                                 */
+    double mass;        /* staggered mass, > 0 when fermions != 0                      */
+    double tau;         /* trajectory length, > 0                                      */
+    int32_t nsteps;     /* molecular-dynamics steps, >= 1                              */
+    int32_t integrator; /* LQS_LEAPFROG or LQS_OMELYAN (second-order minimum norm)     */
+    double lambda;      /* Omelyan parameter (0: 0.1931833275037836)                   */
+    int32_t fermions;   /* 0 pure gauge; 1 pf = eta, phi = m eta_e - D_eo eta_o made   */
+                        /* on the starting links; 2 pf = phi itself (even sites)       */
+    lqs_cg_params cg;   /* the solves chi = M^-1 phi (use_x0: start from the previous  */
+                        /* chi; persistent is ignored)                                 */
+} lqs_hmc_params;
+
+typedef struct {
+    double k0, sg0, sf0;  /* K, S_g, S_f at the start                                   */
+    double k1, sg1, sf1;  /* at the end of the trajectory                               */
+    double dH;            /* (k1 + sg1 + sf1) - (k0 + sg0 + sf0)                        */
+    int32_t accepted;     /* u < exp(-dH)                                               */
+    int32_t cg_solves;    /* solves of M chi = phi                                      */
+    int32_t cg_iters;     /* their inner iterations                                     */
+    int32_t status;       /* worst CG status (LQS_OK when every solve converged)        */
+    double plaquette;     /* mean Re tr P / 3 of the links returned                     */
+    double seconds;       /* wall time of the call                                      */
+} lqs_hmc_stats;
+
+/* One HMC trajectory with the staggered pseudofermion of mass m (one even
+ * field: the determinant of M, four tastes).
+ *   links (in/out): the current links; replaced by the proposal if accepted.
+ *   mom (in/out): the momenta drawn by the caller (anti-Hermitian traceless,
+ *     density ~ exp(tr Q^2)); on return the momenta at the end of the proposal.
+ *   pf: fermions = 1: eta, complex Gaussian with density ~ exp(-eta^dag eta)
+ *     in the lex layout over all sites (nrhs 1); fermions = 2: phi in the lex
+ *     layout (even sites read); ignored (may be NULL) when fermions = 0.
+ *   u: uniform number in [0, 1) for the Metropolis decision.
+ *   proposal (NULL or canonical link layout): receives the proposal.
+ *   phi_out (NULL or lex layout, all sites): receives phi, zero on odd sites.
+ * Leapfrog: Q -= h/2 G, n times {U = exp(hQ)U, Q -= h G} with the last
+ * momentum step h/2; Omelyan: per step Q -= lam h G, U = exp(h/2 Q)U,
+ * Q -= (1-2 lam) h G, U = exp(h/2 Q)U, Q -= lam h G, where G = F/2 on the
+ * current links and h = tau/nsteps; the two lam h updates at a step boundary
+ * act on the same links and share one solve.  The solve for S_f at the start
+ * and end is reused as the force solve on those links.  Returns the worst
+ * CG status (also in stats->status); the call returns when finished. */
+lqs_status hmc_trajectory(lqs_ctx *ctx, const int32_t dims[4], double *links, double *mom, const double *pf,
+                          double u, const lqs_hmc_params *params, lqs_hmc_stats *stats, double *proposal,
+                          double *phi_out, void *stream);
 
 /* ---- diagnostics ------------------------------------------------------- */
 

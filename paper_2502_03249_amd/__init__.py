@@ -57,6 +57,26 @@ class LqsCgStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LqsHmcParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mass", ctypes.c_double), ("tau", ctypes.c_double),
+                ("nsteps", ctypes.c_int32), ("integrator", ctypes.c_int32), ("lam", ctypes.c_double),
+                ("fermions", ctypes.c_int32), ("cg", LqsCgParams)]
+
+
+class LqsHmcStats(ctypes.Structure):
+    _fields_ = [("k0", ctypes.c_double), ("sg0", ctypes.c_double), ("sf0", ctypes.c_double),
+                ("k1", ctypes.c_double), ("sg1", ctypes.c_double), ("sf1", ctypes.c_double),
+                ("dH", ctypes.c_double), ("accepted", ctypes.c_int32), ("cg_solves", ctypes.c_int32),
+                ("cg_iters", ctypes.c_int32), ("status", ctypes.c_int32), ("plaquette", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+LEAPFROG, OMELYAN = 0, 1
+
+
 class LqsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"lqs status {status}: {msg}")
@@ -67,7 +87,8 @@ _lib = None
 EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_create", "lqs_gauge_destroy",
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
            "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
-           "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal"]
+           "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal", "gauge_action", "gauge_force",
+           "link_update", "kinetic_energy", "hmc_trajectory"]
 
 
 def lib():
@@ -104,6 +125,12 @@ def lib():
     L.lqs_last_error.restype = ctypes.c_char_p
     L.lqs_field_dot.argtypes = [vp, i32p, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp, vp]
     L.lqs_profile_hops.argtypes = [vp, i32]
+    L.gauge_action.argtypes = [vp, i32p, vp, d, ctypes.POINTER(d), vp]
+    L.gauge_force.argtypes = [vp, i32p, vp, d, d, i32, vp, vp]
+    L.link_update.argtypes = [vp, i32p, vp, vp, d, vp]
+    L.kinetic_energy.argtypes = [vp, i32p, vp, ctypes.POINTER(d), vp]
+    L.hmc_trajectory.argtypes = [vp, i32p, vp, vp, vp, d, ctypes.POINTER(LqsHmcParams), ctypes.POINTER(LqsHmcStats),
+                                 vp, vp, vp]
     L.lqs_profile_hops_result.argtypes = [vp, i32, i32, d, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(d),
                                           ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
@@ -342,6 +369,75 @@ def field_dot(ctx, a, b, out=None, stream=None):
     _check(lib().lqs_field_dot(ctx.handle, _dims(a.dims), ctypes.byref(ca), ctypes.byref(cb),
                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def _links_tensor(dims, t, what):
+    nx, ny, nz, nt = dims
+    assert t.dtype == torch.complex128 and t.is_contiguous() and tuple(t.shape) == (4, nt, nz, ny, nx, 3, 3), what
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def gauge_action(ctx, dims, links, beta, stream=None):
+    """S_g = beta sum_x sum_{mu<nu} (1 - Re tr P / 3) of complex128 links (4, Nt, Nz, Ny, Nx, 3, 3)."""
+    S = ctypes.c_double()
+    _check(lib().gauge_action(ctx.handle, _dims(dims), _links_tensor(dims, links, "links"), float(beta),
+                              ctypes.byref(S), _stream(stream)))
+    return float(S.value)
+
+
+def gauge_force(ctx, dims, links, beta, coeff=1.0, out=None, accumulate=False, stream=None):
+    """coeff * (beta/3) TA(U V) per link (out = or out +=); returns out."""
+    if out is None:
+        out = torch.empty_like(links)
+    _check(lib().gauge_force(ctx.handle, _dims(dims), _links_tensor(dims, links, "links"), float(beta), float(coeff),
+                             1 if accumulate else 0, _links_tensor(dims, out, "out"), _stream(stream)))
+    return out
+
+
+def link_update(ctx, dims, links, mom, eps, stream=None):
+    """links = exp(eps Q) links in place; returns links."""
+    _check(lib().link_update(ctx.handle, _dims(dims), _links_tensor(dims, links, "links"),
+                             _links_tensor(dims, mom, "mom"), float(eps), _stream(stream)))
+    return links
+
+
+def kinetic_energy(ctx, dims, mom, stream=None):
+    """K = -sum_links tr Q^2."""
+    K = ctypes.c_double()
+    _check(lib().kinetic_energy(ctx.handle, _dims(dims), _links_tensor(dims, mom, "mom"), ctypes.byref(K),
+                                _stream(stream)))
+    return float(K.value)
+
+
+def hmc_trajectory(ctx, dims, links, mom, pf=None, u=0.5, beta=5.5, mass=0.1, tau=1.0, nsteps=10,
+                   integrator=LEAPFROG, lam=0.0, fermions=1, tol=1e-10, max_iter=10000, inner_prec=F64,
+                   inner_recon=18, reliable_interval=0, reliable_delta=0.0, use_x0=False, proposal=None,
+                   phi_out=None, stream=None, check=True):
+    """One HMC trajectory on complex128 links/momenta (updated in place); pf: eta (fermions=1) or phi
+    (fermions=2) as a complex128 lex tensor (Nt, Nz, Ny, Nx, 3).  Returns the stats dict."""
+    nx, ny, nz, nt = dims
+    p = LqsHmcParams(float(beta), float(mass), float(tau), int(nsteps), int(integrator), float(lam), int(fermions),
+                     LqsCgParams(float(tol), int(max_iter), PREC[inner_prec], int(inner_recon),
+                                 int(reliable_interval), float(reliable_delta), 1 if use_x0 else 0, 0))
+    st = LqsHmcStats()
+    pfp = None
+    if fermions:
+        assert pf is not None and pf.dtype == torch.complex128 and pf.is_contiguous()
+        assert tuple(pf.shape) == (nt, nz, ny, nx, 3)
+        pfp = ctypes.c_void_p(pf.data_ptr())
+    prop = _links_tensor(dims, proposal, "proposal") if proposal is not None else None
+    po = None
+    if phi_out is not None:
+        assert phi_out.dtype == torch.complex128 and tuple(phi_out.shape) == (nt, nz, ny, nx, 3)
+        po = ctypes.c_void_p(phi_out.data_ptr())
+    r = lib().hmc_trajectory(ctx.handle, _dims(dims), _links_tensor(dims, links, "links"),
+                             _links_tensor(dims, mom, "mom"), pfp, float(u), ctypes.byref(p), ctypes.byref(st),
+                             prop, po, _stream(stream))
+    if check and r < 0:
+        _check(r)
+    d = st.as_dict()
+    d["return_status"] = int(r)
+    return d
 
 
 def profile_hops(ctx, enable):

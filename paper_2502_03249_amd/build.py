@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblqs.so")
 SOURCES = ["capi.cpp", "tune.cpp", "pack.hip", "dslash.hip", "cg.hip", "force.hip", "persistent.hip",
-           "multishift.hip"]
+           "multishift.hip", "hmc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

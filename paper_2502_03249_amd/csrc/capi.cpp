@@ -9,7 +9,6 @@
 
 namespace lqs {
 
-void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
 void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int recon, int nrhs, hipStream_t s);
 
 static thread_local std::string g_last_error;
@@ -42,12 +41,38 @@ void *Ctx::workspace(const std::string &slot, size_t bytes)
     return p;
 }
 
+void *Ctx::pinned(const std::string &slot, size_t bytes)
+{
+    auto it = pinned_ws.find(slot);
+    if (it != pinned_ws.end() && it->second.second >= bytes) return it->second.first;
+    if (it != pinned_ws.end()) {
+        LQS_HIP(hipDeviceSynchronize());
+        LQS_HIP(hipHostFree(it->second.first));
+        pinned_ws.erase(it);
+    }
+    void *p = nullptr;
+    LQS_HIP(hipHostMalloc(&p, bytes < 256 ? 256 : bytes, hipHostMallocDefault));
+    pinned_ws[slot] = {p, bytes};
+    return p;
+}
+
+hipStream_t Ctx::side_stream(int i)
+{
+    while ((int)side_streams.size() <= i) {
+        hipStream_t st = nullptr;
+        LQS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        side_streams.push_back(st);
+    }
+    return side_streams[i];
+}
+
 Ctx::~Ctx()
 {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
     for (auto &kv : ws) (void)hipFree(kv.second.first);
-    if (host_state) (void)hipHostFree(host_state);
+    for (auto &kv : pinned_ws) (void)hipHostFree(kv.second.first);
+    for (hipStream_t st : side_streams) (void)hipStreamDestroy(st);
     for (auto &e : prof_events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -347,15 +372,13 @@ lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const
             for (int i = 0; i < nprob; ++i) pp.push_back({probs[i].gauge, probs[i].mass, probs[i].b, probs[i].x});
             persistent_solve(*ctx, pp, p, stats, s);
         } else {
-            int off = 0;
-            for (int i = 0; i < nprob; ++i) {
-                if (ctx->tuning) {
+            if (ctx->tuning)
+                for (int i = 0; i < nprob; ++i) {
                     autotune(*ctx, *probs[i].gauge, "hop", p.inner_prec, p.inner_recon, probs[i].nrhs, s);
                     autotune(*ctx, *probs[i].gauge, "normal_dot", p.inner_prec, p.inner_recon, probs[i].nrhs, s);
                 }
-                cg_solve_one(*ctx, probs[i], p, stats + off, s);
-                off += probs[i].nrhs;
-            }
+            if (nprob == 1) cg_solve_one(*ctx, probs[0], p, stats, s);
+            else cg_solve_concurrent(*ctx, nprob, probs, p, stats, s);
         }
         int n = 0;
         for (int i = 0; i < nprob; ++i) n += probs[i].nrhs;
@@ -408,14 +431,14 @@ lqs_status fermion_force(lqs_ctx *ctx, const lqs_gauge *g, const double *X, cons
         check_ptr(X, "X");
         if (Y) check_ptr(Y, "Y");
         check_ptr(force, "force");
-        LQS_REQUIRE(mode == 0 || mode == 1, LQS_EINVAL, "mode must be 0 or 1");
+        LQS_REQUIRE(mode >= 0 && mode <= 2, LQS_EINVAL, "mode must be 0, 1 or 2");
         LQS_REQUIRE(std::isfinite(coeff), LQS_EINVAL, "coeff must be finite");
         hipStream_t s = as_stream(stream);
         const int64_t fb = field_bytes(g->g, F64, 1);
         double *psx = (double *)ctx->workspace("force.psx", fb);
         double *psy = psx;
-        LaunchShape sh = default_hop_shape(F64, 1);
         const LinkRef L = g->ref(F64, 18);
+        const LaunchShape sh = default_hop_shape(L, 1);
         launch_hop_gated(g->g, L, F64, 18, 0, 1, 1, X, psx, nullptr, 0, sh, s);
         if (Y && Y != X) {
             psy = (double *)ctx->workspace("force.psy", fb);
@@ -423,6 +446,120 @@ lqs_status fermion_force(lqs_ctx *ctx, const lqs_gauge *g, const double *X, cons
         }
         launch_force(g->g, L, X, Y ? Y : X, psx, psy, coeff, mode, force, s);
     });
+}
+
+lqs_status gauge_action(lqs_ctx *ctx, const int32_t dims[4], const double *links, double beta, double *S,
+                        void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr && S != nullptr, LQS_EINVAL, "ctx or S is NULL");
+        check_dims(dims);
+        check_ptr(links, "links");
+        LQS_REQUIRE(std::isfinite(beta), LQS_EINVAL, "beta must be finite");
+        LQS_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = as_stream(stream);
+        double *d = (double *)ctx->workspace("api.scalar", sizeof(double) * 2);
+        launch_gauge_action(*ctx, make_geom(dims), links, beta, d, 0, s);
+        LQS_HIP(hipMemcpyAsync(S, d, sizeof(double), hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+lqs_status gauge_force(lqs_ctx *ctx, const int32_t dims[4], const double *links, double beta, double coeff,
+                       int32_t accumulate, double *out, void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
+        check_dims(dims);
+        check_ptr(links, "links");
+        check_ptr(out, "out");
+        LQS_REQUIRE(out != links, LQS_EINVAL, "out must not overlap links");
+        LQS_REQUIRE(accumulate == 0 || accumulate == 1, LQS_EINVAL, "accumulate must be 0 or 1");
+        LQS_REQUIRE(std::isfinite(beta) && std::isfinite(coeff), LQS_EINVAL, "beta and coeff must be finite");
+        LQS_HIP(hipSetDevice(ctx->device));
+        launch_gauge_force(make_geom(dims), links, beta, coeff, accumulate, out, as_stream(stream));
+    });
+}
+
+lqs_status link_update(lqs_ctx *ctx, const int32_t dims[4], double *links, const double *mom, double eps,
+                       void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
+        check_dims(dims);
+        check_ptr(links, "links");
+        check_ptr(mom, "mom");
+        LQS_REQUIRE(mom != links, LQS_EINVAL, "mom must not overlap links");
+        LQS_REQUIRE(std::isfinite(eps), LQS_EINVAL, "eps must be finite");
+        LQS_HIP(hipSetDevice(ctx->device));
+        launch_link_update(make_geom(dims), links, mom, eps, as_stream(stream));
+    });
+}
+
+lqs_status kinetic_energy(lqs_ctx *ctx, const int32_t dims[4], const double *mom, double *K, void *stream)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr && K != nullptr, LQS_EINVAL, "ctx or K is NULL");
+        check_dims(dims);
+        check_ptr(mom, "mom");
+        LQS_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = as_stream(stream);
+        double *d = (double *)ctx->workspace("api.scalar", sizeof(double) * 2);
+        launch_kinetic(*ctx, make_geom(dims), mom, d, 0, s);
+        LQS_HIP(hipMemcpyAsync(K, d, sizeof(double), hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+lqs_status hmc_trajectory(lqs_ctx *ctx, const int32_t dims[4], double *links, double *mom, const double *pf,
+                          double u, const lqs_hmc_params *params, lqs_hmc_stats *stats, double *proposal,
+                          double *phi_out, void *stream)
+{
+    lqs_status worst = LQS_OK;
+    lqs_status st = guard([&] {
+        LQS_REQUIRE(ctx != nullptr && params != nullptr && stats != nullptr, LQS_EINVAL,
+                    "ctx, params or stats is NULL");
+        check_dims(dims);
+        check_ptr(links, "links");
+        check_ptr(mom, "mom");
+        LQS_REQUIRE(mom != links, LQS_EINVAL, "mom must not overlap links");
+        const lqs_hmc_params &p = *params;
+        LQS_REQUIRE(std::isfinite(p.beta) && p.beta >= 0, LQS_EINVAL, "beta must be finite and >= 0");
+        LQS_REQUIRE(std::isfinite(p.tau) && p.tau > 0, LQS_EINVAL, "tau must be positive");
+        LQS_REQUIRE(p.nsteps >= 1, LQS_EINVAL, "nsteps must be >= 1");
+        LQS_REQUIRE(p.integrator == LQS_LEAPFROG || p.integrator == LQS_OMELYAN, LQS_EINVAL, "unknown integrator");
+        LQS_REQUIRE(std::isfinite(p.lambda) && p.lambda >= 0 && p.lambda < 0.5, LQS_EINVAL,
+                    "lambda must be in [0, 0.5)");
+        LQS_REQUIRE(p.fermions >= 0 && p.fermions <= 2, LQS_EINVAL, "fermions must be 0, 1 or 2");
+        LQS_REQUIRE(u >= 0 && u < 1, LQS_EINVAL, "u must be in [0, 1)");
+        if (proposal) {
+            check_ptr(proposal, "proposal");
+            LQS_REQUIRE(proposal != links && proposal != mom, LQS_EINVAL, "proposal must not overlap links or mom");
+        }
+        if (p.fermions) {
+            check_ptr(pf, "pf");
+            LQS_REQUIRE(std::isfinite(p.mass) && p.mass > 0, LQS_EINVAL, "mass must be positive");
+            const lqs_cg_params &c = p.cg;
+            LQS_REQUIRE(c.tol > 0 && std::isfinite(c.tol), LQS_EINVAL, "cg.tol must be positive");
+            LQS_REQUIRE(c.max_iter >= 1, LQS_EINVAL, "cg.max_iter must be >= 1");
+            LQS_REQUIRE(c.inner_prec >= 0 && c.inner_prec <= 2, LQS_EINVAL, "bad cg.inner_prec");
+            LQS_REQUIRE(c.inner_recon == 18 || c.inner_recon == 12, LQS_EINVAL, "cg.inner_recon must be 18 or 12");
+            LQS_REQUIRE(c.reliable_interval >= 0 && c.reliable_delta >= 0 && c.reliable_delta < 1, LQS_EINVAL,
+                        "bad reliable-update parameters");
+            if (phi_out) check_ptr(phi_out, "phi_out");
+        }
+        LQS_HIP(hipSetDevice(ctx->device));
+        lqs_hmc_params q = p;
+        if (!q.fermions) {
+            q.cg.inner_prec = LQS_F64;
+            q.cg.inner_recon = 18;
+        }
+        *stats = lqs_hmc_stats{};
+        hmc_trajectory_impl(*ctx, make_geom(dims), links, mom, pf, u, q, *stats, proposal,
+                            q.fermions ? phi_out : nullptr, as_stream(stream));
+        worst = stats->status;
+    });
+    return st != LQS_OK ? st : worst;
 }
 
 lqs_status lqs_profile_hops(lqs_ctx *ctx, int32_t enable)

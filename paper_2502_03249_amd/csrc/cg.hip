@@ -97,7 +97,7 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 // ---------------------------------------------------------------------------
 // 2. q = m^2 p - D_eo t, <p, q>  (output parity even; t odd)
 
-template <int P, int R, int K, bool TG>
+template <int P, int R, int K, int LF>
 __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, double m2, CgState *st, double *partials,
                                                          int max_blocks, int nrhs)
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, cons
     V3<T> acc[K];
     if (valid) {
         const Site s = decode(g, cb, 0);
-        hop_site<P, R, K, TG>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
+        hop_site<P, R, K, LF>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -385,18 +385,21 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const LinkRef L = gauge.ref(P, R);
     dim3 grid((g.vh + sh.block - 1) / sh.block, (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread);
     const double m2 = v.mass * v.mass;
-#define LQS_ND(K, TG)                                                                                             \
-    hipLaunchKernelGGL((normal_dot_kernel<P, R, K, TG>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
+#define LQS_ND(K, LF)                                                                                             \
+    hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
                        (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs)
-    if (L.temporal) {
-        if (sh.rhs_per_thread == 1) LQS_ND(1, true);
-        else if (sh.rhs_per_thread == 2) LQS_ND(2, true);
-        else LQS_ND(4, true);
-    } else {
-        if (sh.rhs_per_thread == 1) LQS_ND(1, false);
-        else if (sh.rhs_per_thread == 2) LQS_ND(2, false);
-        else LQS_ND(4, false);
+#define LQS_ND_LF(LF)                                                                                            \
+    if (sh.rhs_per_thread == 1) LQS_ND(1, LF);                                                                   \
+    else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \
+    else LQS_ND(4, LF)
+    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
+    switch (lf) {
+    case 0: LQS_ND_LF(0); break;
+    case LF_TEMPORAL: LQS_ND_LF(LF_TEMPORAL); break;
+    case LF_STREAM: LQS_ND_LF(LF_STREAM); break;
+    default: LQS_ND_LF(LF_TEMPORAL | LF_STREAM); break;
     }
+#undef LQS_ND_LF
 #undef LQS_ND
     LQS_HIP(hipGetLastError());
 }
@@ -471,8 +474,9 @@ void cg_residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gat
 {
     (void)ctx;
     if (v.acc_prec != F64 && mode == 0) launch_accumulate(gauge, v, gate_mode == 2 ? 1 : 0, s);
-    LaunchShape sh = default_hop_shape(F64, v.nrhs);
-    launch_hop_gated(gauge.g, gauge.ref(F64, 18), F64, 18, 0, 1, v.nrhs, v.x, v.t64, v.state, gate_mode, sh, s);
+    const LinkRef L64 = gauge.ref(F64, 18);
+    const LaunchShape sh = default_hop_shape(L64, v.nrhs);
+    launch_hop_gated(gauge.g, L64, F64, 18, 0, 1, v.nrhs, v.x, v.t64, v.state, gate_mode, sh, s);
     launch_residual(gauge, v, gate_mode, mode, s);
 }
 
@@ -500,12 +504,11 @@ void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_
 
 void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, bool with_reliable)
 {
-    LaunchShape sh = default_hop_shape(v.prec, v.nrhs);
+    LaunchShape sh = default_hop_shape(gauge.ref(v.prec, v.recon), v.nrhs);
     LaunchShape shd = sh;
     if (ctx.tuner) {
-        LaunchShape t;
-        if (ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, v.prec, v.recon, v.nrhs), t)) sh = t;
-        if (ctx.tuner->lookup(tune_key(ctx, "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), t)) shd = t;
+        ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, v.prec, v.recon, v.nrhs), sh);
+        ctx.tuner->lookup(tune_key(ctx, "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), shd);
     }
     // 1. t = D_oe p
     prof_begin(ctx, s);
@@ -534,132 +537,225 @@ static bool final_phase(int32_t ph)
     return ph == CG_CONVERGED || ph == CG_BREAKDOWN || ph == CG_NONFINITE || ph == CG_MAXITER;
 }
 
-void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
-{
-    auto t0 = std::chrono::steady_clock::now();
-    const Gauge &gauge = *pb.gauge;
-    const Geom &g = gauge.g;
-    const int nrhs = pb.nrhs;
-    const bool mixed = prm.inner_prec != F64;
+// One problem driven as a small state machine, so that several problems on
+// their own streams can be advanced in turn by one host thread.
+namespace {
+
+struct CgRun {
+    Ctx &ctx;
+    lqs_problem pb;
+    lqs_cg_params prm;
+    lqs_cg_stats *stats;
+    hipStream_t s;
+    std::string tag;
+    std::chrono::steady_clock::time_point t0;
     CgVectors v{};
-    v.prec = prm.inner_prec;
-    v.acc_prec = mixed ? F32 : F64;
-    v.recon = prm.inner_recon == 12 ? 12 : 18;
-    v.nrhs = nrhs;
-    v.mass = pb.mass;
-    (void)gauge.ref(v.prec, v.recon);  // format must exist
-    const int64_t fp = field_bytes(g, v.prec, nrhs), fa = field_bytes(g, v.acc_prec, nrhs),
-                  f64 = field_bytes(g, F64, nrhs);
-    v.p = ctx.workspace("cg.p", fp);
-    v.q = ctx.workspace("cg.q", fp);
-    v.t = ctx.workspace("cg.t", fp);
-    v.x = pb.x;
-    v.b = (double *)pb.b;
-    if (mixed) {
-        v.r = ctx.workspace("cg.r", fa);
-        v.xlo = ctx.workspace("cg.xlo", fa);
-        v.t64 = ctx.workspace("cg.t64", f64);
-        v.rhi = nullptr;
-    } else {
-        v.r = ctx.workspace("cg.r", f64);
-        v.xlo = pb.x;
-        v.t64 = v.t;
-        v.rhi = (double *)v.r;
-    }
-    v.max_blocks = cg_partials_needed(gauge, nrhs);
-    v.partials = (double *)ctx.workspace("cg.partials", sizeof(double) * (size_t)v.max_blocks * nrhs);
-    v.state = (CgState *)ctx.workspace("cg.state", sizeof(CgState) * nrhs);
-
-    // initial state records
-    const size_t sbytes = sizeof(CgState) * nrhs;
-    if (ctx.host_state_bytes < 2 * sbytes) {
-        if (ctx.host_state) LQS_HIP(hipHostFree(ctx.host_state));
-        ctx.host_state = nullptr;
-        LQS_HIP(hipHostMalloc(&ctx.host_state, 2 * sbytes, hipHostMallocDefault));
-        ctx.host_state_bytes = 2 * sbytes;
-    }
-    CgState *hs[2] = {(CgState *)ctx.host_state, (CgState *)((char *)ctx.host_state + sbytes)};
-    const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
-    const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.05) : 0.0;
-    for (int r = 0; r < nrhs; ++r) {
-        CgState S{};
-        S.stop2 = prm.tol * prm.tol;
-        S.delta2 = delta * delta;
-        S.rel_interval = rel_interval;
-        S.max_iter = prm.max_iter;
-        S.phase = CG_RUNNING;
-        hs[0][r] = S;
-    }
-    LQS_HIP(hipMemcpyAsync(v.state, hs[0], sbytes, hipMemcpyHostToDevice, s));
-    cg_init(ctx, gauge, v, prm.use_x0 != 0, s);
-
-    // iterate in chunks; the FP64 group closes each chunk; poll the state
-    const int chunk = 4;
-    const int poll_every = 2;  // chunks between polls
-    hipEvent_t ev[2];
-    LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    LQS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    bool mixed = false;
+    int nrhs = 1;
+    size_t sbytes = 0;
+    CgState *hs[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int inflight = 0, slot = 0;
-    int64_t enqueued = 0;
-    const int64_t cap = (int64_t)prm.max_iter + 16 * chunk + 64;
+    int64_t enqueued = 0, cap = 0;
     bool done = false;
-    try {
-        while (!done) {
-            for (int c = 0; c < poll_every; ++c) {
-                for (int i = 0; i < chunk; ++i) cg_iteration(ctx, gauge, v, s, i == chunk - 1);
-                enqueued += chunk;
-            }
-            LQS_HIP(hipMemcpyAsync(hs[slot], v.state, sbytes, hipMemcpyDeviceToHost, s));
-            LQS_HIP(hipEventRecord(ev[slot], s));
-            ++inflight;
-            slot ^= 1;
-            if (inflight == 2) {
-                // wait for the older poll
-                LQS_HIP(hipEventSynchronize(ev[slot]));
-                --inflight;
-                bool all = true;
-                for (int r = 0; r < nrhs; ++r) all &= final_phase(hs[slot][r].phase);
-                if (all || enqueued > cap) done = true;
-            }
-        }
-        LQS_HIP(hipEventSynchronize(ev[slot ^ 1]));
-        LQS_HIP(hipStreamSynchronize(s));
-    } catch (...) {
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
-        throw;
-    }
-    LQS_HIP(hipEventDestroy(ev[0]));
-    LQS_HIP(hipEventDestroy(ev[1]));
+    static constexpr int chunk = 4;       // iterations between FP64 groups
+    static constexpr int poll_every = 2;  // chunks between state polls
 
-    // right-hand sides that stopped without an FP64 check (breakdown,
-    // non-finite, host cap) get x += x_lo and a measured residual
-    LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
-    LQS_HIP(hipStreamSynchronize(s));
-    bool need = false;
-    for (int r = 0; r < nrhs; ++r) need |= !(hs[0][r].phase == CG_CONVERGED || hs[0][r].phase == CG_MAXITER);
-    if (need) {
-        if (mixed) launch_accumulate(gauge, v, 0, s);
-        cg_residual_group(ctx, gauge, v, 0, 2, s);
+    CgRun(Ctx &c, const lqs_problem &p, const lqs_cg_params &pr, lqs_cg_stats *st, hipStream_t str, std::string tg,
+          std::chrono::steady_clock::time_point start)
+        : ctx(c), pb(p), prm(pr), stats(st), s(str), tag(std::move(tg)), t0(start)
+    {
+    }
+    ~CgRun()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    const Gauge &gauge() const { return *pb.gauge; }
+
+    void setup()
+    {
+        const Geom &g = gauge().g;
+        nrhs = pb.nrhs;
+        mixed = prm.inner_prec != F64;
+        v.prec = prm.inner_prec;
+        v.acc_prec = mixed ? F32 : F64;
+        v.recon = prm.inner_recon == 12 ? 12 : 18;
+        v.nrhs = nrhs;
+        v.mass = pb.mass;
+        (void)gauge().ref(v.prec, v.recon);  // format must exist
+        const int64_t fp = field_bytes(g, v.prec, nrhs), fa = field_bytes(g, v.acc_prec, nrhs),
+                      f64 = field_bytes(g, F64, nrhs);
+        v.p = ctx.workspace("cg.p" + tag, fp);
+        v.q = ctx.workspace("cg.q" + tag, fp);
+        v.t = ctx.workspace("cg.t" + tag, fp);
+        v.x = pb.x;
+        v.b = (double *)pb.b;
+        if (mixed) {
+            v.r = ctx.workspace("cg.r" + tag, fa);
+            v.xlo = ctx.workspace("cg.xlo" + tag, fa);
+            v.t64 = ctx.workspace("cg.t64" + tag, f64);
+            v.rhi = nullptr;
+        } else {
+            v.r = ctx.workspace("cg.r" + tag, f64);
+            v.xlo = pb.x;
+            v.t64 = v.t;
+            v.rhi = (double *)v.r;
+        }
+        v.max_blocks = cg_partials_needed(gauge(), nrhs);
+        v.partials = (double *)ctx.workspace("cg.partials" + tag, sizeof(double) * (size_t)v.max_blocks * nrhs);
+        v.state = (CgState *)ctx.workspace("cg.state" + tag, sizeof(CgState) * nrhs);
+        sbytes = sizeof(CgState) * nrhs;
+        char *host = (char *)ctx.pinned("cg.host" + tag, 2 * sbytes);
+        hs[0] = (CgState *)host;
+        hs[1] = (CgState *)(host + sbytes);
+        const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
+        const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.05) : 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            CgState S{};
+            S.stop2 = prm.tol * prm.tol;
+            S.delta2 = delta * delta;
+            S.rel_interval = rel_interval;
+            S.max_iter = prm.max_iter;
+            S.phase = CG_RUNNING;
+            hs[0][r] = S;
+        }
+        LQS_HIP(hipMemcpyAsync(v.state, hs[0], sbytes, hipMemcpyHostToDevice, s));
+        cg_init(ctx, gauge(), v, prm.use_x0 != 0, s);
+        LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        LQS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        cap = (int64_t)prm.max_iter + 16 * chunk + 64;
+    }
+
+    // queue poll_every chunks of iterations and an asynchronous poll of the state
+    void enqueue()
+    {
+        for (int c = 0; c < poll_every; ++c) {
+            for (int i = 0; i < chunk; ++i) cg_iteration(ctx, gauge(), v, s, i == chunk - 1);
+            enqueued += chunk;
+        }
+        LQS_HIP(hipMemcpyAsync(hs[slot], v.state, sbytes, hipMemcpyDeviceToHost, s));
+        LQS_HIP(hipEventRecord(ev[slot], s));
+        ++inflight;
+        slot ^= 1;
+    }
+
+    // with two polls in flight, wait for the older one and decide
+    void check()
+    {
+        if (inflight < 2) return;
+        LQS_HIP(hipEventSynchronize(ev[slot]));
+        --inflight;
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all &= final_phase(hs[slot][r].phase);
+        if (all || enqueued > cap) done = true;
+    }
+
+    void finish()
+    {
+        LQS_HIP(hipStreamSynchronize(s));
+        // right-hand sides that stopped without an FP64 check (breakdown,
+        // non-finite, host cap) get x += x_lo and a measured residual
         LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
         LQS_HIP(hipStreamSynchronize(s));
-    }
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int r = 0; r < nrhs; ++r) {
-        const CgState &S = hs[0][r];
-        lqs_cg_stats &o = stats[r];
-        o.iters = S.iters;
-        o.reliable_updates = S.nreliable;
-        o.restarts = S.restarts;
-        o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
-        o.seconds = secs;
-        switch (S.phase) {
-        case CG_CONVERGED: o.status = LQS_OK; break;
-        case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;
-        case CG_NONFINITE: o.status = LQS_ENONFINITE; break;
-        default: o.status = LQS_ENOTCONV; break;
+        bool need = false;
+        for (int r = 0; r < nrhs; ++r) need |= !(hs[0][r].phase == CG_CONVERGED || hs[0][r].phase == CG_MAXITER);
+        if (need) {
+            if (mixed) launch_accumulate(gauge(), v, 0, s);
+            cg_residual_group(ctx, gauge(), v, 0, 2, s);
+            LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
+            LQS_HIP(hipStreamSynchronize(s));
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int r = 0; r < nrhs; ++r) {
+            const CgState &S = hs[0][r];
+            lqs_cg_stats &o = stats[r];
+            o.iters = S.iters;
+            o.reliable_updates = S.nreliable;
+            o.restarts = S.restarts;
+            o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
+            o.seconds = secs;
+            switch (S.phase) {
+            case CG_CONVERGED: o.status = LQS_OK; break;
+            case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;
+            case CG_NONFINITE: o.status = LQS_ENONFINITE; break;
+            default: o.status = LQS_ENOTCONV; break;
+            }
         }
     }
+};
+
+}  // namespace
+
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
+{
+    CgRun run(ctx, pb, prm, stats, s, "", std::chrono::steady_clock::now());
+    run.setup();
+    try {
+        while (!run.done) {
+            run.enqueue();
+            run.check();
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        throw;
+    }
+    run.finish();
+}
+
+// Problems of different sizes each get a side stream (forked from and joined
+// back into s with events) and their own workspaces; the host enqueues a
+// round of iterations for every unfinished problem before it waits on any
+// poll, so the small lattices' kernels fill the gaps of the large ones.
+void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lqs_cg_params &prm,
+                         lqs_cg_stats *stats, hipStream_t s)
+{
+    constexpr int MAX_SIDE = 8;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nside = nprob < MAX_SIDE ? nprob : MAX_SIDE;
+    hipEvent_t fork = nullptr;
+    LQS_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    std::vector<hipEvent_t> joins;
+    std::vector<std::unique_ptr<CgRun>> runs;
+    auto cleanup = [&]() {
+        for (int k = 0; k < nside; ++k) (void)hipStreamSynchronize(ctx.side_stream(k));
+        for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+        (void)hipEventDestroy(fork);
+    };
+    try {
+        LQS_HIP(hipEventRecord(fork, s));
+        for (int k = 0; k < nside; ++k) LQS_HIP(hipStreamWaitEvent(ctx.side_stream(k), fork, 0));
+        int off = 0;
+        for (int i = 0; i < nprob; ++i) {
+            runs.emplace_back(new CgRun(ctx, probs[i], prm, stats + off, ctx.side_stream(i % nside),
+                                        "#" + std::to_string(i), t0));
+            off += probs[i].nrhs;
+        }
+        for (auto &r : runs) r->setup();
+        bool any = true;
+        while (any) {
+            any = false;
+            for (auto &r : runs)
+                if (!r->done) r->enqueue();
+            for (auto &r : runs)
+                if (!r->done) {
+                    r->check();
+                    any |= !r->done;
+                }
+        }
+        for (auto &r : runs) r->finish();
+        for (int k = 0; k < nside; ++k) {
+            hipEvent_t e = nullptr;
+            LQS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            joins.push_back(e);
+            LQS_HIP(hipEventRecord(e, ctx.side_stream(k)));
+            LQS_HIP(hipStreamWaitEvent(s, e, 0));
+        }
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
 }
 
 }  // namespace lqs

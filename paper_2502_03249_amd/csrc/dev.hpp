@@ -129,6 +129,40 @@ template <typename To, typename From> __device__ __forceinline__ To bitcast(cons
 
 template <typename T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 
+// Streaming loads for the link arrays.  In one operator application every
+// link word is used by exactly one thread; when the links are far larger than
+// the last-level cache (they are not reused from it across applications
+// anyway) they are fetched with the nontemporal hint, so that they do not
+// displace the neighbour colour vectors that nearby threads share.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_stream(const float4 *p)
+{
+    nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ W16 ld_stream(const W16 *p) { return bitcast<W16>(__builtin_nontemporal_load((const nt_u4 *)p)); }
+__device__ __forceinline__ W8 ld_stream(const W8 *p) { return bitcast<W8>(__builtin_nontemporal_load((const nt_u2 *)p)); }
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+template <bool NT, typename T> __device__ __forceinline__ T ld_link(const T *p)
+{
+    if constexpr (NT) return ld_stream(p);
+    else return *p;
+}
+
 __device__ __forceinline__ void h8_to_cx(const W16 &w, Cx<float> *out)
 {
     struct H8 { half_t h[8]; } h = bitcast<H8>(w);
@@ -149,9 +183,9 @@ __device__ __forceinline__ W16 cx_to_h8(const Cx<float> *in)
 
 // Load the link of site cb from a (direction, parity) block; the block base
 // points at word array 0 and vh is the array length.
-template <int P, int R> struct LinkIO;
+template <int P, int R, bool NT = false> struct LinkIO;
 
-template <int R> struct LinkIO<F64, R> {
+template <int R, bool NT> struct LinkIO<F64, R, NT> {
     __device__ static __forceinline__ M3<double> load(const void *base, int64_t vh, int cb)
     {
         const double2 *b = (const double2 *)base;
@@ -159,7 +193,7 @@ template <int R> struct LinkIO<F64, R> {
         constexpr int rows = (R == 12) ? 2 : 3;
 #pragma unroll
         for (int k = 0; k < 3 * rows; ++k) {
-            double2 d = ldg(b + k * vh + cb);
+            double2 d = ld_link<NT>(b + k * vh + cb);
             u.e[k / 3][k % 3] = {d.x, d.y};
         }
         if (R == 12) rebuild_row2(u);
@@ -174,7 +208,7 @@ template <int R> struct LinkIO<F64, R> {
     }
 };
 
-template <int R> struct LinkIO<F32, R> {
+template <int R, bool NT> struct LinkIO<F32, R, NT> {
     __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
     {
         const float4 *b = (const float4 *)base;
@@ -182,7 +216,7 @@ template <int R> struct LinkIO<F32, R> {
         constexpr int n4 = (R == 12) ? 3 : 4;
 #pragma unroll
         for (int k = 0; k < n4; ++k) {
-            float4 d = ldg(b + k * vh + cb);
+            float4 d = ld_link<NT>(b + k * vh + cb);
             u.e[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
             u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
         }
@@ -190,7 +224,7 @@ template <int R> struct LinkIO<F32, R> {
             rebuild_row2(u);
         } else {
             const float2 *t = (const float2 *)(b + 4 * vh);
-            float2 d = ldg(t + cb);
+            float2 d = ld_link<NT>(t + cb);
             u.e[2][2] = {d.x, d.y};
         }
         return u;
@@ -211,23 +245,23 @@ template <int R> struct LinkIO<F32, R> {
     }
 };
 
-template <int R> struct LinkIO<F16, R> {
+template <int R, bool NT> struct LinkIO<F16, R, NT> {
     __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
     {
         const W16 *b = (const W16 *)base;
         M3<float> u;
         Cx<float> e[9];
-        h8_to_cx(ldg(b + cb), e);
+        h8_to_cx(ld_link<NT>(b + cb), e);
         if (R == 12) {
             const W8 *t = (const W8 *)(b + vh);
-            W8 w = ldg(t + cb);
+            W8 w = ld_link<NT>(t + cb);
             struct H4 { half_t h[4]; } h = bitcast<H4>(w);
             e[4] = {(float)h.h[0], (float)h.h[1]};
             e[5] = {(float)h.h[2], (float)h.h[3]};
         } else {
-            h8_to_cx(ldg(b + vh + cb), e + 4);
+            h8_to_cx(ld_link<NT>(b + vh + cb), e + 4);
             const uint32_t *t = (const uint32_t *)(b + 2 * vh);
-            struct H2 { half_t h[2]; } h = bitcast<H2>(ldg(t + cb));
+            struct H2 { half_t h[2]; } h = bitcast<H2>(ld_link<NT>(t + cb));
             e[8] = {(float)h.h[0], (float)h.h[1]};
         }
         constexpr int n = (R == 12) ? 6 : 9;

@@ -20,7 +20,7 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
     return gate[r].reliable_pending != 0;
 }
 
-template <int P, int R, int K, bool DAG, bool TG>
+template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
                                                   const CgState *gate, int gate_mode)
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
     if (!any) return;
     const Site s = decode(g, cb, parity);
     V3<T> acc[K];
-    hop_site<P, R, K, TG>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
+    hop_site<P, R, K, LF>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!active[j]) continue;
@@ -54,20 +54,24 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
 
 template <int P, int R, int K>
 static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs, const void *in, void *out,
-                     const CgState *gate, int gate_mode, int block, hipStream_t s)
+                     const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
     const int64_t stride = field_bytes(g, P, 1);
-    dim3 grid((g.vh + block - 1) / block, (nrhs + K - 1) / K);
-#define LQS_HOP(DAG, TG)                                                                                         \
-    hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, TG>), grid, dim3(block), 0, s, g, L, parity, nrhs,               \
+    dim3 grid((g.vh + sh.block - 1) / sh.block, (nrhs + K - 1) / K);
+    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
+#define LQS_HOP(DAG, LF)                                                                                         \
+    hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), 0, s, g, L, parity, nrhs,            \
                        (const char *)in, stride, (char *)out, stride, gate, gate_mode)
-    if (L.temporal) {
-        if (dagger) LQS_HOP(true, true);
-        else LQS_HOP(false, true);
-    } else {
-        if (dagger) LQS_HOP(true, false);
-        else LQS_HOP(false, false);
+#define LQS_HOP_LF(LF)                                                                                           \
+    if (dagger) LQS_HOP(true, LF);                                                                                \
+    else LQS_HOP(false, LF)
+    switch (lf) {
+    case 0: LQS_HOP_LF(0); break;
+    case LF_TEMPORAL: LQS_HOP_LF(LF_TEMPORAL); break;
+    case LF_STREAM: LQS_HOP_LF(LF_STREAM); break;
+    default: LQS_HOP_LF(LF_TEMPORAL | LF_STREAM); break;
     }
+#undef LQS_HOP_LF
 #undef LQS_HOP
     LQS_HIP(hipGetLastError());
 }
@@ -77,9 +81,9 @@ static void launch_pr(const Geom &g, LinkRef L, int dagger, int parity, int nrhs
                       const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
     switch (sh.rhs_per_thread) {
-    case 1: launch_k<P, R, 1>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
-    case 2: launch_k<P, R, 2>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
-    case 4: launch_k<P, R, 4>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh.block, s); break;
+    case 1: launch_k<P, R, 1>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
+    case 2: launch_k<P, R, 2>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
+    case 4: launch_k<P, R, 4>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
     default: throw Error(LQS_EINVAL, "rhs_per_thread must be 1, 2 or 4");
     }
 }
@@ -97,10 +101,10 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 
 // Shapes the autotuner picked most often on 32^4 and 32^3x8 (every
 // precision): 4 right-hand sides per thread in 64-thread blocks from 4
-// vectors on, 2 per thread in 128-thread blocks for 2-3 vectors.
-LaunchShape default_hop_shape(int prec, int nrhs)
+// vectors on, 2 per thread in 128-thread blocks for 2-3 vectors.  Links are
+// streamed when their footprint exceeds STREAM_LINK_BYTES.
+LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
-    (void)prec;
     LaunchShape sh;
     if (nrhs >= 4) {
         sh.block = 64;
@@ -112,6 +116,7 @@ LaunchShape default_hop_shape(int prec, int nrhs)
         sh.block = 256;
         sh.rhs_per_thread = 1;
     }
+    sh.stream_links = 8 * L.block_bytes >= STREAM_LINK_BYTES ? 1 : 0;
     return sh;
 }
 
@@ -150,14 +155,11 @@ void prof_end(Ctx &ctx, int prec, int recon, int64_t sites, hipStream_t s)
 void launch_hop(Ctx &ctx, const Gauge &gauge, int prec, int recon, int dagger, int out_parity, int nrhs,
                 const void *in, void *out, hipStream_t s, const CgState *gate)
 {
-    LaunchShape sh = default_hop_shape(prec, nrhs);
-    if (ctx.tuner) {
-        LaunchShape t;
-        if (ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, prec, recon, nrhs), t)) sh = t;
-    }
+    const LinkRef L = gauge.ref(prec, recon);
+    LaunchShape sh = default_hop_shape(L, nrhs);
+    if (ctx.tuner) ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, prec, recon, nrhs), sh);
     prof_begin(ctx, s);
-    launch_hop_gated(gauge.g, gauge.ref(prec, recon), prec, recon, dagger, out_parity, nrhs, in, out, gate,
-                     gate ? 1 : 0, sh, s);
+    launch_hop_gated(gauge.g, L, prec, recon, dagger, out_parity, nrhs, in, out, gate, gate ? 1 : 0, sh, s);
     prof_end(ctx, prec, recon, (int64_t)gauge.vh * nrhs, s);
 }
 

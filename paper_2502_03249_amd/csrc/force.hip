@@ -3,7 +3,8 @@
 // provides next to the Dirac operator (Sec. 3).  With psi_X = D_oe X:
 //   y even: Pi_{y,mu} =  eps_mu(y) [psi_X(y+mu) Y(y)^dag + psi_Y(y+mu) X(y)^dag]
 //   y odd : Pi_{y,mu} = -eps_mu(y) [Y(y+mu) psi_X(y)^dag + X(y+mu) psi_Y(y)^dag]
-// mode 0 stores F = coeff * (-TA(U Pi)) (su(3)), mode 1 stores coeff * Pi^dag.
+// mode 0 stores F = coeff * (-TA(U Pi)) (su(3)), mode 1 stores coeff * Pi^dag,
+// mode 2 adds coeff * (-TA(U Pi)) to out (a momentum update).
 // One thread per link; output in the canonical [4][V][3][3] complex layout.
 #include "lqs_impl.hpp"
 
@@ -74,7 +75,15 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, LinkRef L, const cha
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) o[3 * i + j] = make_double2(-coeff * ta[i][j].re, -coeff * ta[i][j].im);
+        for (int j = 0; j < 3; ++j) {
+            double2 r = make_double2(-coeff * ta[i][j].re, -coeff * ta[i][j].im);
+            if (mode == 2) {
+                const double2 p = o[3 * i + j];
+                r.x += p.x;
+                r.y += p.y;
+            }
+            o[3 * i + j] = r;
+        }
 }
 
 void launch_force(const Geom &g, LinkRef links64, const double *X, const double *Y, const double *psx,

@@ -8,19 +8,23 @@
 namespace lqs {
 
 // acc[j] = sum_mu [eps_mu(x) U_{x,mu} in_j(x+mu) - eps_mu(x-mu) U^dag_{x-mu,mu} in_j(x-mu)]
-// for the site cb of parity `parity` (decoded into s).  TG: the links are in
-// temporal gauge (U_t = 1 off the last time slice) and those t-links are
-// neither read nor multiplied; without TG every link is read (also correct
-// for temporal-gauge links, just slower).  Inactive right-hand
+// for the site cb of parity `parity` (decoded into s).  LF holds link flags:
+// LF_TEMPORAL, the links are in temporal gauge (U_t = 1 off the last time
+// slice) and those t-links are neither read nor multiplied (without it every
+// link is read, also correct for temporal-gauge links, just slower);
+// LF_STREAM, link words are fetched with streaming loads.  Inactive right-hand
 // sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
 // the input field (parity 1 - parity); consecutive sides are in_stride bytes
 // apart.
-template <int P, int R, int K, bool TG = false>
+enum { LF_TEMPORAL = 1, LF_STREAM = 2 };
+
+template <int P, int R, int K, int LF = 0>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
                                          const char *in, int64_t in_stride, const bool *active,
                                          V3<typename RealOf<P>::type> *acc)
 {
     typedef typename RealOf<P>::type T;
+    constexpr bool TG = (LF & LF_TEMPORAL) != 0, NT = (LF & LF_STREAM) != 0;
     const char *lb = (const char *)L.base;
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = vzero<T>();
@@ -35,7 +39,7 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
             for (int j = 0; j < K; ++j)
                 if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]), nf);
         } else {
-            const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+            const M3<T> uf = LinkIO<P, R, NT>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!active[j]) continue;
@@ -48,7 +52,7 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
             for (int j = 0; j < K; ++j)
                 if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]), nb);
         } else {
-            const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
+            const M3<T> ub = LinkIO<P, R, NT>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!active[j]) continue;

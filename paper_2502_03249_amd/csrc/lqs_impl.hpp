@@ -99,9 +99,10 @@ struct Ctx {
     std::unique_ptr<Tuner> tuner;
     // workspace buffers by slot, grown on demand, freed with the context
     std::map<std::string, std::pair<void *, size_t>> ws;
-    // pinned host mirror of CG states
-    void *host_state = nullptr;
-    size_t host_state_bytes = 0;
+    // pinned host buffers by slot (CG state mirrors), freed with the context
+    std::map<std::string, std::pair<void *, size_t>> pinned_ws;
+    // side streams for concurrent solves (default priority, non-blocking)
+    std::vector<hipStream_t> side_streams;
     // hop profiling: per (prec, recon) sums of event-timed launches
     bool profiling = false;
     struct ProfSlot {
@@ -115,6 +116,8 @@ struct Ctx {
     size_t prof_used = 0;
 
     void *workspace(const std::string &slot, size_t bytes);
+    void *pinned(const std::string &slot, size_t bytes);
+    hipStream_t side_stream(int i);
     ~Ctx();
 };
 
@@ -153,10 +156,15 @@ void launch_field_dot(Ctx &ctx, const Geom &g, int nrhs, const void *a, const vo
 struct LaunchShape {
     int block = 256;       // threads per block
     int rhs_per_thread = 1;
+    int stream_links = 0;  // 1: link words fetched with streaming (nontemporal) loads
 };
+// Link footprint from which the hop streams its links by default: beyond
+// about three quarters of the 256 MB last-level cache (MALL) the links of one
+// application are no longer there at the next one.
+constexpr int64_t STREAM_LINK_BYTES = 192ll << 20;
 void launch_hop(Ctx &ctx, const Gauge &gauge, int prec, int recon, int dagger, int out_parity, int nrhs,
                 const void *in, void *out, hipStream_t s, const CgState *gate);
-LaunchShape default_hop_shape(int prec, int nrhs);
+LaunchShape default_hop_shape(const LinkRef &L, int nrhs);
 void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger, int parity, int nrhs,
                       const void *in, void *out, const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s);
 void launch_hop_shape(const Geom &g, LinkRef links, int prec, int recon, int dagger, int out_parity, int nrhs,
@@ -195,6 +203,22 @@ struct PersistentProblem {
 void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, const lqs_cg_params &prm,
                       lqs_cg_stats *stats, hipStream_t s);
 
+// cg.hip: one problem with the multi-kernel iteration (returns when done)
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
+// several problems, each on its own side stream, iterated concurrently
+void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lqs_cg_params &prm,
+                         lqs_cg_stats *stats, hipStream_t s);
+
+// hmc.hip (canonical [4][V][3][3] complex128 links and momenta)
+void launch_gauge_action(Ctx &ctx, const Geom &g, const double *U, double beta, double *out, int slot, hipStream_t s);
+void launch_kinetic(Ctx &ctx, const Geom &g, const double *Q, double *out, int slot, hipStream_t s);
+void launch_gauge_force(const Geom &g, const double *U, double beta, double coeff, int accumulate, double *out,
+                        hipStream_t s);
+void launch_link_update(const Geom &g, double *U, const double *Q, double eps, hipStream_t s);
+void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, const double *pf, double u,
+                         const lqs_hmc_params &prm, lqs_hmc_stats &st, double *proposal, double *phi_out,
+                         hipStream_t s);
+
 // multishift.hip
 void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *masses, const double *b, double *const *x,
                       const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
@@ -202,9 +226,9 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
 // tune.cpp
 struct Tuner {
     std::string path;
-    std::map<std::string, std::string> cache;  // key -> "block,rhs_per_thread"
+    std::map<std::string, std::string> cache;  // key -> "block,rhs_per_thread,stream_links"
     explicit Tuner(const char *p);
-    bool lookup(const std::string &key, LaunchShape &out) const;
+    bool lookup(const std::string &key, LaunchShape &out, int max_block = 512) const;
     void store(const std::string &key, const LaunchShape &v);
     void save() const;
 };

@@ -28,7 +28,6 @@
 namespace lqs {
 
 void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape sh, hipStream_t s);
-void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
 
 static constexpr int MS_MAX = 16;
 static constexpr int MS_BLOCK = 256;
@@ -272,7 +271,7 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     hipLaunchKernelGGL(ms_finalize_init, dim3(1), dim3(1024), 0, s, v.state, (const double *)v.partials, blocks);
     LQS_HIP(hipGetLastError());
 
-    const LaunchShape sh = default_hop_shape(F64, 1);
+    const LaunchShape sh = default_hop_shape(gauge.ref(F64, 18), 1);
     const int nd_blocks = (vh + sh.block - 1) / sh.block;
     CgState hs{};
     int64_t enqueued = 0;

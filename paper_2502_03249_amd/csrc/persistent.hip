@@ -490,7 +490,7 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
                "x" + std::to_string(d.g.n[3]);
     LaunchShape best{256, 2};
     LaunchShape t;
-    if (ctx.tuner && ctx.tuner->lookup(key, t)) {
+    if (ctx.tuner && ctx.tuner->lookup(key, t, 1024)) {
         best = t;
     } else if (ctx.tuning && ctx.tuner) {
         double best_s = 1e30;

@@ -2,9 +2,10 @@
 //
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
-// thread) with HIP events on the caller's stream, keeps the one with the
-// lowest median time, and stores it in a flat JSON object
-// {"key": "block,rhs_per_thread", ...} that later runs load.  Tuning runs
+// thread x cached or streaming link loads) with HIP events on the caller's
+// stream, keeps the one with the lowest median time, and stores it in a flat
+// JSON object {"key": "block,rhs_per_thread,stream_links", ...} that later
+// runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
 #include <cstring>
@@ -40,21 +41,26 @@ Tuner::Tuner(const char *p)
     }
 }
 
-bool Tuner::lookup(const std::string &key, LaunchShape &out) const
+// On a hit the stored fields replace those of `out`; an entry without the
+// third field keeps out.stream_links.
+bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) const
 {
     auto it = cache.find(key);
     if (it == cache.end()) return false;
-    int b = 0, k = 0;
-    if (std::sscanf(it->second.c_str(), "%d,%d", &b, &k) != 2) return false;
-    if (b < 64 || b > 512 || (b & 63) || !(k == 1 || k == 2 || k == 4)) return false;
+    int b = 0, k = 0, st = out.stream_links;
+    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d", &b, &k, &st);
+    if (n < 2) return false;
+    if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1)) return false;
     out.block = b;
     out.rhs_per_thread = k;
+    out.stream_links = st;
     return true;
 }
 
 void Tuner::store(const std::string &key, const LaunchShape &v)
 {
-    cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread);
+    cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread) + "," +
+                 std::to_string(v.stream_links);
 }
 
 void Tuner::save() const
@@ -87,7 +93,8 @@ static std::vector<LaunchShape> candidates(int nrhs)
     std::vector<LaunchShape> c;
     for (int k : {1, 2, 4}) {
         if (k > nrhs) break;
-        for (int b : {64, 128, 256, 512}) c.push_back({b, k});
+        for (int b : {64, 128, 256, 512})
+            for (int st : {0, 1}) c.push_back({b, k, st});
     }
     return c;
 }
@@ -132,7 +139,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LQS_HIP(hipEventCreate(&e1));
     const LinkRef L = gauge.ref(prec, recon);
     float best = 1e30f;
-    LaunchShape best_shape = default_hop_shape(prec, nrhs);
+    LaunchShape best_shape = default_hop_shape(L, nrhs);
     for (const LaunchShape &c : candidates(nrhs)) {
         std::vector<float> t;
         for (int rep = 0; rep < 7; ++rep) {

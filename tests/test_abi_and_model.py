@@ -67,21 +67,31 @@ def test_null_handles_rejected_before_any_launch(L):
     assert L.fermion_force(None, None, None, None, ctypes.c_double(1.0), 0, None, None) == -1
     L.lqs_last_error.restype = ctypes.c_char_p
     assert b"NULL" in L.lqs_last_error()
+    for name, args in (("gauge_action", (None, None, None, ctypes.c_double(1.0), None, None)),
+                       ("kinetic_energy", (None, None, None, None, None)),
+                       ("hmc_trajectory", (None, None, None, None, None, ctypes.c_double(0.5), None, None, None,
+                                           None, None))):
+        fn = getattr(L, name)
+        fn.restype = ctypes.c_int32
+        assert fn(*args) == -1
 
 
 def test_ctypes_structs_match_c_layout(tmp_path):
     import paper_2502_03249_amd as lqs
     src = tmp_path / "sz.c"
     src.write_text('#include "lqs.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lqs_field), sizeof(lqs_problem), '
+                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lqs_field), sizeof(lqs_problem), '
                    'sizeof(lqs_cg_params), sizeof(lqs_cg_stats), offsetof(lqs_cg_params, reliable_delta), '
-                   'offsetof(lqs_cg_stats, true_rel_residual));return 0;}\n')
+                   'offsetof(lqs_cg_stats, true_rel_residual), sizeof(lqs_hmc_params), sizeof(lqs_hmc_stats), '
+                   'offsetof(lqs_hmc_params, cg), offsetof(lqs_hmc_stats, plaquette), '
+                   'offsetof(lqs_hmc_params, fermions));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(lqs.LqsField), ctypes.sizeof(lqs.LqsProblem), ctypes.sizeof(lqs.LqsCgParams),
             ctypes.sizeof(lqs.LqsCgStats), lqs.LqsCgParams.reliable_delta.offset,
-            lqs.LqsCgStats.true_rel_residual.offset]
+            lqs.LqsCgStats.true_rel_residual.offset, ctypes.sizeof(lqs.LqsHmcParams), ctypes.sizeof(lqs.LqsHmcStats),
+            lqs.LqsHmcParams.cg.offset, lqs.LqsHmcStats.plaquette.offset, lqs.LqsHmcParams.fermions.offset]
     assert got == want
 
 

@@ -64,7 +64,7 @@ def test_cg_parameter_checks(setup):
     assert _status(lambda: lqs.cg_solve(ctx, [(g, 0.1, b, x)], inner_recon=8)) == lqs.EINVAL
     assert _status(lambda: lqs.cg_solve(ctx, [(g, -1.0, b, x)])) == lqs.EINVAL
     assert _status(lambda: lqs.cg_solve(ctx, [(g64, 0.1, b, x)], inner_prec=lqs.F16)) == lqs.EUNSUPPORTED
-    assert _status(lambda: lqs.fermion_force(ctx, g, b, None, 1.0, mode=2)) == lqs.EINVAL
+    assert _status(lambda: lqs.fermion_force(ctx, g, b, None, 1.0, mode=3)) == lqs.EINVAL
 
 
 def test_nonfinite_source_reported(setup):

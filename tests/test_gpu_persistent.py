@@ -1,4 +1,5 @@
-"""Several lattices of uneven size in one cooperative launch.
+"""Several lattices of uneven size in one cooperative launch, and the multi-kernel batch
+that runs them concurrently on side streams.
 
 Each lattice must reach the FP64 true residual on its own (recomputed by the
 oracle) and agree with its standalone multi-kernel solve to within
@@ -97,3 +98,40 @@ def test_persistent_rejects_multi_rhs_and_warm_start(ctx):
     with pytest.raises(lqs.LqsError) as e:
         lqs.cg_solve(ctx, [(g, 0.1, b1, b1.like().zero_())], persistent=True, use_x0=True)
     assert e.value.status == lqs.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [lqs.F64, lqs.F16])
+def test_concurrent_uneven_batch_equals_standalone(ctx, prec):
+    """The multi-kernel batch runs each lattice on its own stream; every solution is bit-identical
+    to the lattice's standalone solve (same kernels, same fixed-order reductions)."""
+    probs, host = _setup(ctx, BATCH)
+    st = lqs.cg_solve(ctx, probs, tol=1e-10, inner_prec=prec, reliable_interval=100)
+    for (g, mass, bf, xf), (dims, U, m, b), s in zip(probs, host, st):
+        assert s["status"] == 0, s
+        x = lex_of(ctx, xf)
+        assert oracle.true_residual(dims, U, m, b, x) <= 1e-10
+        xs = bf.like().zero_()
+        s1 = lqs.cg_solve(ctx, [(g, m, bf, xs)], tol=1e-10, inner_prec=prec, reliable_interval=100)
+        assert s1[0]["iters"] == s["iters"]
+        assert np.array_equal(x, lex_of(ctx, xs))
+
+
+def test_concurrent_many_small_problems_share_streams(ctx):
+    """Ten problems (more than the side streams), one with four right-hand sides."""
+    specs = [((4, 4, 4, 4), 0.1 + 0.05 * k, 1100 + k, 2100 + k) for k in range(9)]
+    probs, host = _setup(ctx, specs)
+    dims4 = (4, 6, 8, 10)
+    U4 = synth.gauge(dims4, "haar", seed=1199)
+    b4 = np.stack([synth.source(dims4, 0, seed=2199 + k) for k in range(4)])
+    g4 = gauge(ctx, dims4, U4)
+    bf4 = field(ctx, dims4, b4, 0)
+    xf4 = bf4.like().zero_()
+    st = lqs.cg_solve(ctx, probs + [(g4, 0.2, bf4, xf4)], tol=1e-10, inner_prec=lqs.F32, reliable_interval=50)
+    assert len(st) == 9 + 4
+    for (g, mass, bf, xf), (dims, U, m, b), s in zip(probs, host, st):
+        assert s["status"] == 0
+        assert oracle.true_residual(dims, U, m, b, lex_of(ctx, xf)) <= 1e-10
+    x4 = lex_of(ctx, xf4, squeeze=False)
+    for k in range(4):
+        assert st[9 + k]["status"] == 0
+        assert oracle.true_residual(dims4, U4, 0.2, b4[k], x4[k]) <= 1e-10

@@ -3,10 +3,11 @@ import json
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import synth
-from gpu_util import field, gauge, lex_of
+from gpu_util import field, gauge, lex_of, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +42,8 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
     assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
     for v in entries.values():
-        blk, k = (int(t) for t in v.split(","))
-        assert blk in (64, 128, 256, 512) and k in (1, 2, 4)
+        blk, k, st = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1)
 
     # the persistent multi-lattice solve tunes its resident blocks per compute unit
     tuned = lqs.Context(0, tune_cache=cache, tuning=True)
@@ -60,12 +61,68 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
         assert oracle.true_residual(d_, U_, m_, b_, lex_of(tuned, xx)) <= 1e-10
     tuned.close()
     entries = json.load(open(cache))
-    assert any("|persistent|p1|r18|8x8x8x16|4x6x8x10" in k for k in entries)
+    pkeys = [k for k in entries if "|persistent|p1|r18|8x8x8x16|4x6x8x10" in k]
+    assert len(pkeys) == 1
+    blk, bpc, _ = (int(t) for t in entries[pkeys[0]].split(","))
+    assert blk in (256, 512, 1024) and bpc in (1, 2, 4)
 
     # a new context loads the cache and does not need to tune again
     again = lqs.Context(0, tune_cache=cache, tuning=True)
     g2 = gauge(again, dims, U)
     got2 = lex_of(again, lqs.dslash_apply(again, g2, field(again, dims, srcs, 1)), squeeze=False)
     assert np.array_equal(got2, ref)
+    # every stored persistent shape (a 1024-thread one included) is read back, not re-tuned
+    again.close()
+    entries[pkeys[0]] = "1024,1,0"
+    with open(cache, "w") as f:
+        json.dump(entries, f)
+    again = lqs.Context(0, tune_cache=cache, tuning=True)
+    probs = []
+    for d_, U_, b_ in ((dims, U, b), (dims2, U2, b2)):
+        gg = gauge(again, d_, U_)
+        bb = field(again, d_, b_, 0)
+        probs.append((gg, 0.1, bb, bb.like().zero_()))
+    st = lqs.cg_solve(again, probs, tol=1e-10, inner_prec=lqs.F32, reliable_interval=100, persistent=True)
+    assert all(s_["status"] == 0 for s_ in st)
     again.close()
     assert json.load(open(cache)) == entries
+
+
+@pytest.mark.parametrize("prec,recon,bound", [(lqs.F64, 18, 1e-12), (lqs.F32, 12, 2e-6), (lqs.F16, 12, 4e-3)])
+def test_streaming_link_loads(tmp_path, prec, recon, bound):
+    """Cached and streaming link loads read the same words: the hop agrees with the oracle either way
+    and the two agree to rounding (the compiler may contract a few products differently, so the
+    FP32 and FP16 kernels need not match bit for bit); CG converges to the same solution."""
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "haar", seed=95)
+    srcs = np.stack([synth.source(dims, 1, seed=950 + k) for k in range(2)])
+    b = synth.source(dims, 0, seed=96)
+    want = np.stack([oracle.dslash(dims, U, srcs[k], 0) for k in range(2)])
+    out = []
+    for st in (0, 1):
+        cache = str(tmp_path / f"tune{st}.json")
+        key_arch = torch.cuda.get_device_properties(0).gcnArchName.replace('"', "_")
+        entries = {}
+        for kern, n in (("hop", 2), ("hop", 1), ("normal_dot", 1)):
+            entries[f"{key_arch}|{kern}|8x8x8x16|p{prec}|r{recon}|n{n}"] = f"128,{n},{st}"
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache, tuning=False)
+        g = gauge(ctx, dims, U)
+        y = lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, srcs, 1, prec), recon=recon), squeeze=False)
+        for k in range(2):
+            assert rel(y[k], want[k]) <= bound
+        bf = field(ctx, dims, b, 0)
+        xf = bf.like().zero_()
+        res = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=prec, inner_recon=recon,
+                           reliable_interval=100)
+        assert res[0]["status"] == 0
+        x = lex_of(ctx, xf)
+        assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+        out.append((y, x))
+        ctx.close()
+        assert json.load(open(cache)) == entries
+    eps = {lqs.F64: 1e-15, lqs.F32: 1e-6, lqs.F16: 1e-3}[prec]
+    assert rel(out[0][0], out[1][0]) <= eps
+    # both solutions satisfy ||x - x*|| <= kappa tol ||x*||, kappa <= (m^2 + 64) / m^2
+    assert rel(out[0][1], out[1][1]) <= 2 * (mass ** 2 + 64) / mass ** 2 * 1e-10
