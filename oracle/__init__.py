@@ -56,6 +56,8 @@ def load():
     lib.ora_force.restype = None
     lib.ora_threads.argtypes = []
     lib.ora_threads.restype = i32
+    lib.ora_set_threads.argtypes = [i32]
+    lib.ora_set_threads.restype = None
     lib.ora_expm3.argtypes = [vp, vp]
     lib.ora_expm3.restype = None
     lib.ora_plaquette_action.argtypes = [i32p, vp, d]
@@ -153,6 +155,11 @@ def force(dims, U, X, Y=None, coeff=1.0, mode=0):
 
 def threads():
     return int(load().ora_threads())
+
+
+def set_threads(n):
+    """Threads for the oracle's parallel regions."""
+    load().ora_set_threads(int(n))
 
 
 OMELYAN_LAMBDA = 0.1931833275037836

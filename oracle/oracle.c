@@ -376,6 +376,16 @@ void ora_force(const int32_t dims[4], const double *U, const double *X, const do
     free(psy);
 }
 
+/* Threads for the oracle's parallel regions (n >= 1; no effect without OpenMP). */
+void ora_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region of the oracle uses (1 without OpenMP). */
 int32_t ora_threads(void)
 {

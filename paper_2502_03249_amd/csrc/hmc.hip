@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(HMC_BLOCK) gauge_force_kernel(Geom g, int vol,
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) v.e[i][j] = {0.0, 0.0};
+#pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu) continue;
         // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag

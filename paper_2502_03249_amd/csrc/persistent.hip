@@ -488,7 +488,7 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
     for (const PLat &d : L)
         key += "|" + std::to_string(d.g.n[0]) + "x" + std::to_string(d.g.n[1]) + "x" + std::to_string(d.g.n[2]) +
                "x" + std::to_string(d.g.n[3]);
-    LaunchShape best{256, 2};
+    LaunchShape best{1024, 1};  // the shape the search picks on the uneven 16^4 / 24^3x8 / 32^3x8 batch
     LaunchShape t;
     if (ctx.tuner && ctx.tuner->lookup(key, t, 1024)) {
         best = t;
