@@ -85,6 +85,9 @@ Gauge::~Gauge()
     for (auto &row : fmt)
         for (auto &p : row)
             if (p) (void)hipFree(p);
+    for (auto &row : unit)
+        for (auto &p : row)
+            if (p) (void)hipFree(p);
 }
 
 }  // namespace lqs
@@ -233,6 +236,10 @@ lqs_status lqs_gauge_create(lqs_ctx *ctx, const int32_t dims[4], const double *l
                     const size_t bytes = (size_t)link_block_bytes_per_site(prec, recon) * g->vh * 8;
                     LQS_HIP(hipMalloc(&g->fmt[prec][rc], bytes));
                     launch_pack_links(g->g, links, prec, recon, g->fmt[prec][rc], as_stream(stream));
+                    if (temporal) {
+                        LQS_HIP(hipMalloc(&g->unit[prec][rc], 256));
+                        launch_unit_link(prec, recon, g->unit[prec][rc], as_stream(stream));
+                    }
                 }
         } catch (...) {
             delete g;

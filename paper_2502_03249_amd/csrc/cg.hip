@@ -383,6 +383,9 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const Geom &g = gauge.g;
     const int64_t stride = field_bytes(g, P, 1);
     const LinkRef L = gauge.ref(P, R);
+    // temporal gauge: one right-hand side per thread spills (as in the hop),
+    // the two-sided kernel with the second side inactive does not
+    if (L.temporal && sh.rhs_per_thread == 1) sh.rhs_per_thread = 2;
     dim3 grid((g.vh + sh.block - 1) / sh.block, (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread);
     const double m2 = v.mass * v.mass;
 #define LQS_ND(K, LF)                                                                                             \
@@ -507,8 +510,9 @@ void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, boo
     LaunchShape sh = default_hop_shape(gauge.ref(v.prec, v.recon), v.nrhs);
     LaunchShape shd = sh;
     if (ctx.tuner) {
-        ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, v.prec, v.recon, v.nrhs), sh);
-        ctx.tuner->lookup(tune_key(ctx, "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), shd);
+        const bool tg = gauge.temporal;
+        ctx.tuner->lookup(tune_key(ctx, tg ? "hop_tg" : "hop", gauge.g, v.prec, v.recon, v.nrhs), sh);
+        ctx.tuner->lookup(tune_key(ctx, tg ? "normal_dot_tg" : "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), shd);
     }
     // 1. t = D_oe p
     prof_begin(ctx, s);

@@ -38,6 +38,16 @@ template <typename T> struct M3 {
     Cx<T> e[3][3];
 };
 
+template <typename T> __device__ __forceinline__ M3<T> m3_unit()
+{
+    M3<T> u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) u.e[i][j] = {(T)(i == j ? 1 : 0), (T)0};
+    return u;
+}
+
 template <typename T> __device__ __forceinline__ V3<T> vzero()
 {
     V3<T> v;

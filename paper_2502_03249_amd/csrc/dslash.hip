@@ -80,7 +80,11 @@ template <int P, int R>
 static void launch_pr(const Geom &g, LinkRef L, int dagger, int parity, int nrhs, const void *in, void *out,
                       const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
-    switch (sh.rhs_per_thread) {
+    // The temporal-gauge kernel with one right-hand side per thread keeps the
+    // links of all directions live and spills (256 VGPRs); the two-sided
+    // kernel with the second side inactive does not (116 VGPRs).
+    const int k = (L.temporal && sh.rhs_per_thread == 1) ? 2 : sh.rhs_per_thread;
+    switch (k) {
     case 1: launch_k<P, R, 1>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
     case 2: launch_k<P, R, 2>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
     case 4: launch_k<P, R, 4>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
@@ -157,7 +161,7 @@ void launch_hop(Ctx &ctx, const Gauge &gauge, int prec, int recon, int dagger, i
 {
     const LinkRef L = gauge.ref(prec, recon);
     LaunchShape sh = default_hop_shape(L, nrhs);
-    if (ctx.tuner) ctx.tuner->lookup(tune_key(ctx, "hop", gauge.g, prec, recon, nrhs), sh);
+    if (ctx.tuner) ctx.tuner->lookup(tune_key(ctx, gauge.temporal ? "hop_tg" : "hop", gauge.g, prec, recon, nrhs), sh);
     prof_begin(ctx, s);
     launch_hop_gated(gauge.g, L, prec, recon, dagger, out_parity, nrhs, in, out, gate, gate ? 1 : 0, sh, s);
     prof_end(ctx, prec, recon, (int64_t)gauge.vh * nrhs, s);

@@ -10,7 +10,7 @@ namespace lqs {
 // acc[j] = sum_mu [eps_mu(x) U_{x,mu} in_j(x+mu) - eps_mu(x-mu) U^dag_{x-mu,mu} in_j(x-mu)]
 // for the site cb of parity `parity` (decoded into s).  LF holds link flags:
 // LF_TEMPORAL, the links are in temporal gauge (U_t = 1 off the last time
-// slice) and those t-links are neither read nor multiplied (without it every
+// slice) and those t-links are not read from the link arrays (without it every
 // link is read, also correct for temporal-gauge links, just slower);
 // LF_STREAM, link words are fetched with streaming loads.  Inactive right-hand
 // sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
@@ -33,32 +33,28 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
         const bool nf = (s.negf >> mu) & 1;
         const bool nb = !((s.negb >> mu) & 1);
         // temporal gauge (Sec. 4.3): the t-links are unit matrices except on
-        // the last time slice, so they are neither read nor multiplied
-        if (TG && mu == 3 && (s.tunit & 1u)) {
+        // the last time slice; they are not read from the link arrays, the
+        // one stored unit link (vh = 1, always cached) is read instead.
+        // Selecting the address keeps the code free of branches (a branch
+        // around the product quadruples the register count of this loop).
+        const bool uf_unit = TG && mu == 3 && (s.tunit & 1u);
+        const bool ub_unit = TG && mu == 3 && (s.tunit & 2u);
+        const M3<T> uf = LinkIO<P, R, NT>::load(uf_unit ? (const char *)L.unit : lb + (2 * mu + parity) * L.block_bytes,
+                                                uf_unit ? 1 : g.vh, uf_unit ? 0 : cb);
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]), nf);
-        } else {
-            const M3<T> uf = LinkIO<P, R, NT>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if (!active[j]) continue;
-                const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
-                accum(acc[j], mv(uf, v), nf);
-            }
+        for (int j = 0; j < K; ++j) {
+            if (!active[j]) continue;
+            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
+            accum(acc[j], mv(uf, v), nf);
         }
-        if (TG && mu == 3 && (s.tunit & 2u)) {
+        const M3<T> ub = LinkIO<P, R, NT>::load(ub_unit ? (const char *)L.unit
+                                                        : lb + (2 * mu + 1 - parity) * L.block_bytes,
+                                                ub_unit ? 1 : g.vh, ub_unit ? 0 : s.bwd[mu]);
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (active[j]) accum(acc[j], SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]), nb);
-        } else {
-            const M3<T> ub = LinkIO<P, R, NT>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if (!active[j]) continue;
-                const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
-                accum(acc[j], mdv(ub, v), nb);
-            }
+        for (int j = 0; j < K; ++j) {
+            if (!active[j]) continue;
+            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
+            accum(acc[j], mdv(ub, v), nb);
         }
     }
 }

@@ -7,6 +7,29 @@
 
 namespace lqs {
 
+// ---------------------------------------------------------------------------
+// one unit link in a link format's layout with vh = 1 (the temporal-gauge
+// hop reads it in place of the unit t-links, so that skipping them needs no
+// branch around the product)
+
+template <int P, int R> __global__ void unit_link_kernel(void *out)
+{
+    M3<typename RealOf<P>::type> u = m3_unit<typename RealOf<P>::type>();
+    LinkIO<P, R>::store(out, 1, 0, u);
+}
+
+void launch_unit_link(int prec, int recon, void *out, hipStream_t s)
+{
+    if (prec == F64 && recon == 18) hipLaunchKernelGGL((unit_link_kernel<F64, 18>), dim3(1), dim3(1), 0, s, out);
+    else if (prec == F64) hipLaunchKernelGGL((unit_link_kernel<F64, 12>), dim3(1), dim3(1), 0, s, out);
+    else if (prec == F32 && recon == 18) hipLaunchKernelGGL((unit_link_kernel<F32, 18>), dim3(1), dim3(1), 0, s, out);
+    else if (prec == F32) hipLaunchKernelGGL((unit_link_kernel<F32, 12>), dim3(1), dim3(1), 0, s, out);
+    else if (recon == 18) hipLaunchKernelGGL((unit_link_kernel<F16, 18>), dim3(1), dim3(1), 0, s, out);
+    else hipLaunchKernelGGL((unit_link_kernel<F16, 12>), dim3(1), dim3(1), 0, s, out);
+    LQS_HIP(hipGetLastError());
+}
+
+
 template <int P, int R>
 __global__ void pack_links_kernel(Geom g, const double2 *canon, char *out, int64_t block_bytes)
 {

@@ -102,7 +102,9 @@ static std::vector<LaunchShape> candidates(int nrhs)
 void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int recon, int nrhs, hipStream_t s)
 {
     if (!ctx.tuner) return;
-    const std::string key = tune_key(ctx, kernel, gauge.g, prec, recon, nrhs);
+    // temporal-gauge links get their own entries (a different kernel variant)
+    const std::string key =
+        tune_key(ctx, (std::string(kernel) + (gauge.temporal ? "_tg" : "")).c_str(), gauge.g, prec, recon, nrhs);
     LaunchShape found;
     if (ctx.tuner->lookup(key, found)) return;
     const bool is_dot = std::strcmp(kernel, "normal_dot") == 0;
