@@ -100,12 +100,15 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 template <int P, int R, int K, int LF>
 __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, double m2, CgState *st, double *partials,
-                                                         int max_blocks, int nrhs)
+                                                         int max_blocks, int nrhs, int ngroups)
 {
     typedef typename RealOf<P>::type T;
-    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    int tile, grp;
+    tile_group(ngroups, tile, grp);
+    if (tile * (int)blockDim.x >= g.vh) return;  // padding tile (whole block)
+    const int cb = tile * blockDim.x + threadIdx.x;
     const bool valid = cb < g.vh;
-    const int r0 = blockIdx.y * K;
+    const int r0 = grp * K;
     bool blk[K], act[K];
     bool any = false;
 #pragma unroll
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, cons
         if (!blk[j]) continue;
         const int r = r0 + j;
         const double s = block_sum(dot[j]);
-        if (threadIdx.x == 0) partials[(int64_t)r * max_blocks + blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[(int64_t)r * max_blocks + tile] = s;
     }
 }
 
@@ -386,11 +389,12 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     // temporal gauge: one right-hand side per thread spills (as in the hop),
     // the two-sided kernel with the second side inactive does not
     if (L.temporal && sh.rhs_per_thread == 1) sh.rhs_per_thread = 2;
-    dim3 grid((g.vh + sh.block - 1) / sh.block, (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread);
+    const int tiles = (g.vh + sh.block - 1) / sh.block, G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
+    const dim3 grid(tile_group_blocks(tiles, G));
     const double m2 = v.mass * v.mass;
 #define LQS_ND(K, LF)                                                                                             \
     hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
-                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs)
+                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G)
 #define LQS_ND_LF(LF)                                                                                            \
     if (sh.rhs_per_thread == 1) LQS_ND(1, LF);                                                                   \
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \

@@ -23,12 +23,14 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
 template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
-                                                  const CgState *gate, int gate_mode)
+                                                  const CgState *gate, int gate_mode, int ngroups)
 {
     typedef typename RealOf<P>::type T;
-    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    int tile, grp;
+    tile_group(ngroups, tile, grp);
+    const int cb = tile * blockDim.x + threadIdx.x;
     if (cb >= g.vh) return;
-    const int r0 = blockIdx.y * K;
+    const int r0 = grp * K;
     bool active[K];
     bool any = false;
 #pragma unroll
@@ -57,11 +59,12 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
                      const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
     const int64_t stride = field_bytes(g, P, 1);
-    dim3 grid((g.vh + sh.block - 1) / sh.block, (nrhs + K - 1) / K);
+    const int tiles = (g.vh + sh.block - 1) / sh.block, G = (nrhs + K - 1) / K;
+    const dim3 grid(tile_group_blocks(tiles, G));
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
 #define LQS_HOP(DAG, LF)                                                                                         \
     hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), 0, s, g, L, parity, nrhs,            \
-                       (const char *)in, stride, (char *)out, stride, gate, gate_mode)
+                       (const char *)in, stride, (char *)out, stride, gate, gate_mode, G)
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
     else LQS_HOP(false, LF)
@@ -106,7 +109,9 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 // Shapes the autotuner picked most often on 32^4 and 32^3x8 (every
 // precision): 4 right-hand sides per thread in 64-thread blocks from 4
 // vectors on, 2 per thread in 128-thread blocks for 2-3 vectors.  Links are
-// streamed when their footprint exceeds STREAM_LINK_BYTES.
+// streamed when their footprint exceeds STREAM_LINK_BYTES and one group of
+// right-hand sides covers all of them; with several groups the blocks of one
+// site tile reuse the links from L2 (see tile_group) and cached loads win.
 LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
     LaunchShape sh;
@@ -120,7 +125,7 @@ LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
         sh.block = 256;
         sh.rhs_per_thread = 1;
     }
-    sh.stream_links = 8 * L.block_bytes >= STREAM_LINK_BYTES ? 1 : 0;
+    sh.stream_links = (8 * L.block_bytes >= STREAM_LINK_BYTES && nrhs <= sh.rhs_per_thread) ? 1 : 0;
     return sh;
 }
 

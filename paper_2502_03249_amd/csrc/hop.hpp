@@ -18,6 +18,26 @@ namespace lqs {
 // apart.
 enum { LF_TEMPORAL = 1, LF_STREAM = 2 };
 
+// Block -> (site tile, right-hand-side group) for launches over several
+// groups of right-hand sides.  The G blocks of one site tile are 8 block
+// indices apart: the round-robin dispatch over the 8 XCDs puts them on the
+// same XCD in close succession, so the links they share come from HBM once
+// and then from that XCD's L2.  The grid has ceil(tiles / 8) * 8 * G blocks;
+// tiles past the last are empty.  With G == 1 the map is the identity.
+__device__ __forceinline__ void tile_group(int G, int &tile, int &grp)
+{
+    if (G == 1) {
+        tile = blockIdx.x;
+        grp = 0;
+        return;
+    }
+    const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+    grp = q % G;
+    tile = (q / G) * 8 + xcd;
+}
+
+inline unsigned tile_group_blocks(int tiles, int G) { return G == 1 ? tiles : ((tiles + 7) / 8) * 8 * G; }
+
 template <int P, int R, int K, int LF = 0>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
                                          const char *in, int64_t in_stride, const bool *active,
