@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--dims", default=None, help="override lattice, e.g. 32,32,32,8")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads (size sweep, multi-RHS, batches, force); one JSON line each")
+    ap.add_argument("--suite-only", default=None,
+                    help="comma-separated suite sections: hop_sweep, cg_sweep, nmulti, temporal, multishift, "
+                         "block_cg, uneven, small_cg, reliable, force, oracle, hmc")
     return ap.parse_args()
 
 
@@ -307,6 +310,10 @@ def run_suite(a):
 
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
     ctx = lqs.Context(0, tune_cache=os.path.join(ROOT, "gpurun_out", "tune_suite.json"))
+    only = set(a.suite_only.split(",")) if a.suite_only else None
+
+    def want(name):
+        return only is None or name in only
 
     def setup(dims, kind, lseed, sseeds, mass=None, formats=lqs.FMT_ALL):
         U = synth.gauge(dims, kind, seed=lseed, eps=0.3)
@@ -317,267 +324,282 @@ def run_suite(a):
         return U, g, b
 
     # 1. hop size sweep (the hop at every format, standalone, stream events)
-    for dims in [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 8), (24, 24, 24, 24),
-                 (32, 32, 32, 32), (48, 48, 48, 12), (64, 64, 64, 16)]:
-        U, g, _ = setup(dims, "smooth", 1002, [7])
-        vh = int(np.prod(dims)) // 2
-        for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f16", 18), ("f16", 12)]:
-            pr = lqs.PREC[prec]
-            x = lqs.Field.from_lex(ctx, torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev), 1, pr)
-            y = x.like(parity=0)
-            ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 20)
-            mb = model.hop_model_bytes(pr, recon)
-            emit({"suite": "hop_size_sweep", "dims": dims, "prec": prec, "recon": recon, "us": round(1e3 * ms, 2),
-                  "model_GBps": round(mb * vh / ms / 1e6, 1), "GFLOPs": round(570 * vh / ms / 1e6, 1),
-                  "note": "lattice links fit in the 256 MB MALL" if mb * vh < 2.5e8 else "HBM"})
-        g.close()
+    if want("hop_sweep"):
+        for dims in [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 8), (24, 24, 24, 24),
+                     (32, 32, 32, 32), (48, 48, 48, 12), (64, 64, 64, 16)]:
+            U, g, _ = setup(dims, "smooth", 1002, [7])
+            vh = int(np.prod(dims)) // 2
+            for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f16", 18), ("f16", 12)]:
+                pr = lqs.PREC[prec]
+                x = lqs.Field.from_lex(ctx, torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev), 1, pr)
+                y = x.like(parity=0)
+                ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 20)
+                mb = model.hop_model_bytes(pr, recon)
+                emit({"suite": "hop_size_sweep", "dims": dims, "prec": prec, "recon": recon, "us": round(1e3 * ms, 2),
+                      "model_GBps": round(mb * vh / ms / 1e6, 1), "GFLOPs": round(570 * vh / ms / 1e6, 1),
+                      "note": "lattice links fit in the 256 MB MALL" if mb * vh < 2.5e8 else "HBM"})
+            g.close()
 
     # 1b. CG size sweep (the CG curve of Fig. 3): time per iteration and algorithmic GB/s of the
-    #     FP64 solver and the FP16-mixed solver, 8^4 .. 64^3x16, m 0.05
-    for dims in [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 24), (32, 32, 32, 32), (48, 48, 48, 12),
-                 (64, 64, 64, 16)]:
-        U, g, b = setup(dims, "smooth", 1002, [2002])
-        vh = int(np.prod(dims)) // 2
-        x = b.like()
-        for inner, recon in (("f64", 18), ("f16", 12)):
-            pr = lqs.PREC[inner]
-            lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr, inner_recon=recon,
-                         reliable_interval=100)
-            st = []
-            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr,
-                                                     inner_recon=recon, reliable_interval=100)), 2)
-            it = st[-1][0]["iters"]
-            by = model.cg_iteration_bytes(pr, lqs.F64 if pr == lqs.F64 else lqs.F32, recon) * vh
-            emit({"suite": "cg_size_sweep", "dims": dims, "inner": inner, "recon": recon, "s": round(t, 5),
-                  "iters": it, "us_per_iter": round(1e6 * t / it, 2), "alg_GBps": round(by * it / t / 1e9, 1),
-                  "true_res": st[-1][0]["true_rel_residual"]})
-        g.close()
+    if want("cg_sweep"):
+        #     FP64 solver and the FP16-mixed solver, 8^4 .. 64^3x16, m 0.05
+        for dims in [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 24), (32, 32, 32, 32), (48, 48, 48, 12),
+                     (64, 64, 64, 16)]:
+            U, g, b = setup(dims, "smooth", 1002, [2002])
+            vh = int(np.prod(dims)) // 2
+            x = b.like()
+            for inner, recon in (("f64", 18), ("f16", 12)):
+                pr = lqs.PREC[inner]
+                lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr, inner_recon=recon,
+                             reliable_interval=100)
+                st = []
+                t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr,
+                                                         inner_recon=recon, reliable_interval=100)), 2)
+                it = st[-1][0]["iters"]
+                by = model.cg_iteration_bytes(pr, lqs.F64 if pr == lqs.F64 else lqs.F32, recon) * vh
+                emit({"suite": "cg_size_sweep", "dims": dims, "inner": inner, "recon": recon, "s": round(t, 5),
+                      "iters": it, "us_per_iter": round(1e6 * t / it, 2), "alg_GBps": round(by * it / t / 1e9, 1),
+                      "true_res": st[-1][0]["true_rel_residual"]})
+            g.close()
 
     # 2. multi-vector hop: 32^4 (the paper's Table 2 lattice) and 32^3x8 with 16 sources
-    for dims in [(32, 32, 32, 32), (32, 32, 32, 8)]:
-        U, g, _ = setup(dims, "smooth", 1001, [7])
+    if want("nmulti"):
+        for dims in [(32, 32, 32, 32), (32, 32, 32, 8)]:
+            U, g, _ = setup(dims, "smooth", 1001, [7])
+            vh = int(np.prod(dims)) // 2
+            srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
+            for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12)]:
+                pr = lqs.PREC[prec]
+                for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+                    x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
+                    y = x.like(parity=0)
+                    for tuned in (False, True):
+                        ctx.set_tuning(tuned)
+                        ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
+                        emit({"suite": "nmulti", "dims": dims, "prec": prec, "recon": recon, "n": n, "tuned": tuned,
+                              "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
+                              "model_GBps": round(model.hop_model_bytes(pr, recon, n) * vh / ms / 1e6, 1)})
+                    ctx.set_tuning(False)
+            g.close()
+
+    # 2b. the paper's Table 2 storage: 32^4 in temporal gauge, 12-real links (6 links read per
+    if want("temporal"):
+        #     site off the last time slice), FP64 and FP32, n = 1..16, tuned shapes
+        dims = (32, 32, 32, 32)
+        U = synth.gauge(dims, "smooth", seed=1001, eps=0.3)
+        Uf, _ = lqs.gauge_fix_temporal(ctx, dims, torch.from_numpy(U).to(dev))
+        g = lqs.Gauge(ctx, dims, Uf, lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
         vh = int(np.prod(dims)) // 2
         srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
-        for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12)]:
+        lps = 6 + 2 / dims[3]
+        ctx.set_tuning(True)
+        for prec, recon in [("f64", 12), ("f32", 12), ("f64", 18), ("f32", 18), ("f16", 12)]:
             pr = lqs.PREC[prec]
             for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
                 x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
                 y = x.like(parity=0)
-                for tuned in (False, True):
-                    ctx.set_tuning(tuned)
-                    ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
-                    emit({"suite": "nmulti", "dims": dims, "prec": prec, "recon": recon, "n": n, "tuned": tuned,
-                          "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
-                          "model_GBps": round(model.hop_model_bytes(pr, recon, n) * vh / ms / 1e6, 1)})
-                ctx.set_tuning(False)
+                ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
+                emit({"suite": "nmulti_temporal", "dims": dims, "prec": prec, "recon": recon, "n": n,
+                      "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
+                      "model_GBps": round(model.hop_model_bytes(pr, recon, n, lps) * vh / ms / 1e6, 1)})
+        ctx.set_tuning(False)
         g.close()
-
-    # 2b. the paper's Table 2 storage: 32^4 in temporal gauge, 12-real links (6 links read per
-    #     site off the last time slice), FP64 and FP32, n = 1..16, tuned shapes
-    dims = (32, 32, 32, 32)
-    U = synth.gauge(dims, "smooth", seed=1001, eps=0.3)
-    Uf, _ = lqs.gauge_fix_temporal(ctx, dims, torch.from_numpy(U).to(dev))
-    g = lqs.Gauge(ctx, dims, Uf, lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
-    vh = int(np.prod(dims)) // 2
-    srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
-    lps = 6 + 2 / dims[3]
-    ctx.set_tuning(True)
-    for prec, recon in [("f64", 12), ("f32", 12), ("f64", 18), ("f32", 18), ("f16", 12)]:
-        pr = lqs.PREC[prec]
-        for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
-            x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
-            y = x.like(parity=0)
-            ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
-            emit({"suite": "nmulti_temporal", "dims": dims, "prec": prec, "recon": recon, "n": n,
-                  "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
-                  "model_GBps": round(model.hop_model_bytes(pr, recon, n, lps) * vh / ms / 1e6, 1)})
-    ctx.set_tuning(False)
-    g.close()
-    del Uf
+        del Uf
 
     # 2c. several masses on one Krylov space vs one solve per mass (64^3x16, FP64)
-    dims = DIMS
-    U, g, b = setup(dims, "smooth", 1002, [2002])
-    masses = [0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0]
-    xs = [b.like() for _ in masses]
-    st = []
-    t_ms = timed(lambda: st.append(lqs.cg_solve_multishift(ctx, g, masses, b, xs, tol=TOL)), 2)
-    t_sep = 0.0
-    for m_, x_ in zip(masses, xs):
-        t_sep += timed(lambda: lqs.cg_solve(ctx, [(g, m_, b, x_.zero_())], tol=TOL, inner_prec=lqs.F64), 1)
-    emit({"suite": "multishift", "dims": dims, "masses": masses, "multishift_s": round(t_ms, 4),
-          "separate_fp64_s": round(t_sep, 4), "speedup": round(t_sep / t_ms, 2),
-          "iters": [r["iters"] for r in st[-1]], "true_res": [r["true_rel_residual"] for r in st[-1]],
-          "all_converged": all(r["status"] == 0 for r in st[-1])})
-    g.close()
-
-    # 3. 16-RHS block CG on 32^3x8 (m 0.02) vs 16 single solves, FP32 inner + FP64 reliable updates
-    dims, mass = (32, 32, 32, 8), 0.02
-    U, g, b = setup(dims, "smooth", 1001, [2100 + k for k in range(16)])
-    x = b.like()
-    for prec in ("f32", "f16", "f64"):
+    if want("multishift"):
+        dims = DIMS
+        U, g, b = setup(dims, "smooth", 1002, [2002])
+        masses = [0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0]
+        xs = [b.like() for _ in masses]
         st = []
-        t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.PREC[prec],
-                                                 reliable_interval=100)), 2)
-        singles = 0.0
-        for k in range(16):
-            bk = lqs.Field(dims, lqs.F64, 0, 1, data=b.data[k * lqs.field_bytes(dims, lqs.F64):
-                                                          (k + 1) * lqs.field_bytes(dims, lqs.F64)])
-            xk = bk.like()
-            singles += timed(lambda: lqs.cg_solve(ctx, [(g, mass, bk, xk.zero_())], tol=TOL,
-                                                  inner_prec=lqs.PREC[prec], reliable_interval=100), 1)
-        s = st[-1]
-        emit({"suite": "block_cg_16rhs", "dims": dims, "mass": mass, "inner": prec, "block_s": round(t, 4),
-              "sixteen_singles_s": round(singles, 4), "speedup": round(singles / t, 2),
-              "iters": [r["iters"] for r in s], "max_true_res": max(r["true_rel_residual"] for r in s),
-              "all_converged": all(r["status"] == 0 for r in s)})
-    g.close()
-
-    # 4. uneven batch: one persistent launch vs three multi-kernel solves
-    specs = [((16, 16, 16, 16), 0.05, 1031, 2031), ((24, 24, 24, 8), 0.02, 1032, 2032),
-             ((32, 32, 32, 8), 0.01, 1033, 2033)]
-    probs = []
-    for d_, m_, ls, ss in specs:
-        _, g_, b_ = setup(d_, "smooth", ls, [ss])
-        probs.append((g_, m_, b_, b_.like()))
-    for prec, tuned in (("f32", False), ("f32", True), ("f16", False), ("f16", True), ("f64", False)):
-        pr = lqs.PREC[prec]
-        st = []
-        ctx.set_tuning(tuned)
-        # one untimed call first: it runs the shape search when tuning is on
-        lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL, inner_prec=pr,
-                     reliable_interval=100, persistent=True)
-        tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
-                                                  tol=TOL, inner_prec=pr, reliable_interval=100,
-                                                  persistent=True)), 3)
-        ctx.set_tuning(False)
-        # one call, multi-kernel: the lattices run concurrently on side streams
-        ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
-                                        inner_prec=pr, reliable_interval=100), 3)
-
-        def sequential():
-            for g_, m_, b_, x_ in probs:
-                lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_())], tol=TOL, inner_prec=pr, reliable_interval=100)
-        tq = timed(sequential, 3)
-        emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
-              "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5),
-              "concurrent_multikernel_s": round(ts, 5), "sequential_s": round(tq, 5),
-              "persistent_vs_sequential": round(tq / tp, 2), "concurrent_vs_sequential": round(tq / ts, 2),
-              "iters": [r["iters"] for r in st[-1]],
-              "true_res": [r["true_rel_residual"] for r in st[-1]],
+        t_ms = timed(lambda: st.append(lqs.cg_solve_multishift(ctx, g, masses, b, xs, tol=TOL)), 2)
+        t_sep = 0.0
+        for m_, x_ in zip(masses, xs):
+            t_sep += timed(lambda: lqs.cg_solve(ctx, [(g, m_, b, x_.zero_())], tol=TOL, inner_prec=lqs.F64), 1)
+        emit({"suite": "multishift", "dims": dims, "masses": masses, "multishift_s": round(t_ms, 4),
+              "separate_fp64_s": round(t_sep, 4), "speedup": round(t_sep / t_ms, 2),
+              "iters": [r["iters"] for r in st[-1]], "true_res": [r["true_rel_residual"] for r in st[-1]],
               "all_converged": all(r["status"] == 0 for r in st[-1])})
-    for g_, _, _, _ in probs:
-        g_.close()
-
-    # 5. small-lattice and 32^3x8 FP64 CG (multi-kernel and persistent)
-    for dims, kind, ls, ss, mass in [((4, 4, 4, 4), "haar", 1000, 2000, 0.1), ((32, 32, 32, 8), "smooth", 1001, 2001, 0.02)]:
-        U, g, b = setup(dims, kind, ls, [ss])
-        x = b.like()
-        for persistent in (False, True):
-            st = []
-            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F64,
-                                                     persistent=persistent)), 3)
-            emit({"suite": "cg_fp64", "dims": dims, "mass": mass, "persistent": persistent, "s": round(t, 5),
-                  "iters": st[-1][0]["iters"], "true_res": st[-1][0]["true_rel_residual"]})
-        tm = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
-                                                  reliable_interval=100, inner_recon=12)), 3)
-        emit({"suite": "cg_mixed_f16", "dims": dims, "mass": mass, "s": round(tm, 5), "iters": st[-1][0]["iters"],
-              "true_res": st[-1][0]["true_rel_residual"]})
         g.close()
 
-    # 6. reliable-update interval K and threshold delta for the 64^3x16 FP16 solve
-    dims, mass = DIMS, MASS
-    U, g, b = setup(dims, "smooth", 1002, [2002])
-    x = b.like()
-    for K in (50, 100, 200, 400):
-        for delta in (0.1, 0.05, 0.01):
+    # 3. 16-RHS block CG on 32^3x8 (m 0.02) vs 16 single solves, FP32 inner + FP64 reliable updates
+    if want("block_cg"):
+        dims, mass = (32, 32, 32, 8), 0.02
+        U, g, b = setup(dims, "smooth", 1001, [2100 + k for k in range(16)])
+        x = b.like()
+        for prec in ("f32", "f16", "f64"):
             st = []
-            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
-                                                     inner_recon=12, reliable_interval=K, reliable_delta=delta)), 2)
-            r = st[-1][0]
-            emit({"suite": "reliable_sweep", "dims": dims, "K": K, "delta": delta, "s": round(t, 5),
-                  "iters": r["iters"], "reliable_updates": r["reliable_updates"],
-                  "true_res": r["true_rel_residual"], "status": r["status"]})
-    g.close()
+            t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.PREC[prec],
+                                                     reliable_interval=100)), 2)
+            singles = 0.0
+            for k in range(16):
+                bk = lqs.Field(dims, lqs.F64, 0, 1, data=b.data[k * lqs.field_bytes(dims, lqs.F64):
+                                                              (k + 1) * lqs.field_bytes(dims, lqs.F64)])
+                xk = bk.like()
+                singles += timed(lambda: lqs.cg_solve(ctx, [(g, mass, bk, xk.zero_())], tol=TOL,
+                                                      inner_prec=lqs.PREC[prec], reliable_interval=100), 1)
+            s = st[-1]
+            emit({"suite": "block_cg_16rhs", "dims": dims, "mass": mass, "inner": prec, "block_s": round(t, 4),
+                  "sixteen_singles_s": round(singles, 4), "speedup": round(singles / t, 2),
+                  "iters": [r["iters"] for r in s], "max_true_res": max(r["true_rel_residual"] for r in s),
+                  "all_converged": all(r["status"] == 0 for r in s)})
+        g.close()
+
+    # 4. uneven batch: one persistent launch vs three multi-kernel solves
+    if want("uneven"):
+        specs = [((16, 16, 16, 16), 0.05, 1031, 2031), ((24, 24, 24, 8), 0.02, 1032, 2032),
+                 ((32, 32, 32, 8), 0.01, 1033, 2033)]
+        probs = []
+        for d_, m_, ls, ss in specs:
+            _, g_, b_ = setup(d_, "smooth", ls, [ss])
+            probs.append((g_, m_, b_, b_.like()))
+        for prec, tuned in (("f32", False), ("f32", True), ("f16", False), ("f16", True), ("f64", False)):
+            pr = lqs.PREC[prec]
+            st = []
+            ctx.set_tuning(tuned)
+            # one untimed call first: it runs the shape search when tuning is on
+            lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL, inner_prec=pr,
+                         reliable_interval=100, persistent=True)
+            tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
+                                                      tol=TOL, inner_prec=pr, reliable_interval=100,
+                                                      persistent=True)), 3)
+            ctx.set_tuning(False)
+            # one call, multi-kernel: the lattices run concurrently on side streams
+            ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
+                                            inner_prec=pr, reliable_interval=100), 3)
+
+            def sequential():
+                for g_, m_, b_, x_ in probs:
+                    lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_())], tol=TOL, inner_prec=pr, reliable_interval=100)
+            tq = timed(sequential, 3)
+            emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
+                  "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5),
+                  "concurrent_multikernel_s": round(ts, 5), "sequential_s": round(tq, 5),
+                  "persistent_vs_sequential": round(tq / tp, 2), "concurrent_vs_sequential": round(tq / ts, 2),
+                  "iters": [r["iters"] for r in st[-1]],
+                  "true_res": [r["true_rel_residual"] for r in st[-1]],
+                  "all_converged": all(r["status"] == 0 for r in st[-1])})
+        for g_, _, _, _ in probs:
+            g_.close()
+
+    # 5. small-lattice and 32^3x8 FP64 CG (multi-kernel and persistent)
+    if want("small_cg"):
+        for dims, kind, ls, ss, mass in [((4, 4, 4, 4), "haar", 1000, 2000, 0.1), ((32, 32, 32, 8), "smooth", 1001, 2001, 0.02)]:
+            U, g, b = setup(dims, kind, ls, [ss])
+            x = b.like()
+            for persistent in (False, True):
+                st = []
+                t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F64,
+                                                         persistent=persistent)), 3)
+                emit({"suite": "cg_fp64", "dims": dims, "mass": mass, "persistent": persistent, "s": round(t, 5),
+                      "iters": st[-1][0]["iters"], "true_res": st[-1][0]["true_rel_residual"]})
+            tm = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
+                                                      reliable_interval=100, inner_recon=12)), 3)
+            emit({"suite": "cg_mixed_f16", "dims": dims, "mass": mass, "s": round(tm, 5), "iters": st[-1][0]["iters"],
+                  "true_res": st[-1][0]["true_rel_residual"]})
+            g.close()
+
+    # 6. reliable-update interval K and threshold delta for the 64^3x16 FP16 solve
+    if want("reliable"):
+        dims, mass = DIMS, MASS
+        U, g, b = setup(dims, "smooth", 1002, [2002])
+        x = b.like()
+        for K in (50, 100, 200, 400):
+            for delta in (0.1, 0.05, 0.01):
+                st = []
+                t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, mass, b, x.zero_())], tol=TOL, inner_prec=lqs.F16,
+                                                         inner_recon=12, reliable_interval=K, reliable_delta=delta)), 2)
+                r = st[-1][0]
+                emit({"suite": "reliable_sweep", "dims": dims, "K": K, "delta": delta, "s": round(t, 5),
+                      "iters": r["iters"], "reliable_updates": r["reliable_updates"],
+                      "true_res": r["true_rel_residual"], "status": r["status"]})
+        g.close()
 
     # 7. differentiation: 24^4, m 0.05: action (CG), adjoint force
-    from paper_2502_03249_amd.autograd import staggered_action
-    dims, mass = (24, 24, 24, 24), 0.05
-    U = synth.gauge(dims, "smooth", seed=1004, eps=0.3)
-    Ut = torch.from_numpy(U).to(dev).requires_grad_(True)
-    phi = torch.from_numpy(synth.source(dims, 0, seed=2004)).to(dev).requires_grad_(True)
+    if want("force"):
+        from paper_2502_03249_amd.autograd import staggered_action
+        dims, mass = (24, 24, 24, 24), 0.05
+        U = synth.gauge(dims, "smooth", seed=1004, eps=0.3)
+        Ut = torch.from_numpy(U).to(dev).requires_grad_(True)
+        phi = torch.from_numpy(synth.source(dims, 0, seed=2004)).to(dev).requires_grad_(True)
 
-    def fwd_bwd():
-        Ut.grad = None
-        phi.grad = None
-        S = staggered_action(Ut, phi, mass, ctx, project=True, tol=1e-10)
-        S.backward()
-    t = timed(fwd_bwd, 3)
-    g = lqs.Gauge(ctx, dims, Ut.detach(), lqs.fmt("f64", 18))
-    X = lqs.Field.from_lex(ctx, phi.detach(), 0)
-    out = torch.empty_like(Ut.detach())
-    ms = event_ms(lambda: lqs.fermion_force(ctx, g, X, None, 1.0, 0, out), 10)
-    # the oracle on the host: hop at 32^3x8, 24^4 and 64^3x16 with one thread and all threads,
-    # CG at 4^4 (full) -- the CPU baseline of the GPU numbers above
-    import oracle
-    nthr = oracle.threads()
-    for dh in [(32, 32, 32, 8), (24, 24, 24, 24), (64, 64, 64, 16)]:
-        Uh = synth.gauge(dh, "smooth", seed=1001, eps=0.3)
-        xh = synth.source(dh, 1, seed=7)
-        res = {}
-        for nt_ in (1, nthr):
-            oracle.set_threads(nt_)
-            t0 = time.perf_counter()
-            oracle.dslash(dh, Uh, xh, 0)
-            res[nt_] = time.perf_counter() - t0
-        oracle.set_threads(nthr)
-        vhh = int(np.prod(dh)) // 2
-        emit({"suite": "oracle_hop", "dims": dh, "s_1_thread": round(res[1], 4), "s_all": round(res[nthr], 4),
-              "threads": nthr, "GFLOPs_all": round(570 * vhh / res[nthr] / 1e9, 3),
-              "model_GBps_all": round(1584 * vhh / res[nthr] / 1e9, 3)})
-        del Uh, xh
-    U4 = synth.gauge((4, 4, 4, 4), "haar", seed=1000)
-    b4 = synth.source((4, 4, 4, 4), 0, seed=2000)
-    t0 = time.perf_counter()
-    _, st4, it4, tr4 = oracle.cg((4, 4, 4, 4), U4, 0.1, b4, tol=TOL)
-    emit({"suite": "oracle_cg_4x4", "s": round(time.perf_counter() - t0, 4), "iters": it4, "true_res": tr4,
-          "threads": nthr})
+        def fwd_bwd():
+            Ut.grad = None
+            phi.grad = None
+            S = staggered_action(Ut, phi, mass, ctx, project=True, tol=1e-10)
+            S.backward()
+        t = timed(fwd_bwd, 3)
+        g = lqs.Gauge(ctx, dims, Ut.detach(), lqs.fmt("f64", 18))
+        X = lqs.Field.from_lex(ctx, phi.detach(), 0)
+        out = torch.empty_like(Ut.detach())
+        ms = event_ms(lambda: lqs.fermion_force(ctx, g, X, None, 1.0, 0, out), 10)
+        emit({"suite": "force_24x4", "action_forward_backward_s": round(t, 4), "fermion_force_call_ms": round(ms, 4),
+              "note": "fermion_force = one D_oe hop + the outer-product/projection kernel"})
+        del g, X, out
 
-    emit({"suite": "force_24x4", "action_forward_backward_s": round(t, 4), "fermion_force_call_ms": round(ms, 4),
-          "note": "fermion_force = one D_oe hop + the outer-product/projection kernel"})
-    del g, X, out
+    # 7b. the oracle on the host: hop at 32^3x8, 24^4 and 64^3x16 with one thread and all threads,
+    #     CG at 4^4 (full) -- the CPU baseline of the GPU numbers above
+    if want("oracle"):
+        import oracle
+        nthr = oracle.threads()
+        for dh in [(32, 32, 32, 8), (24, 24, 24, 24), (64, 64, 64, 16)]:
+            Uh = synth.gauge(dh, "smooth", seed=1001, eps=0.3)
+            xh = synth.source(dh, 1, seed=7)
+            res = {}
+            for nt_ in (1, nthr):
+                oracle.set_threads(nt_)
+                t0 = time.perf_counter()
+                oracle.dslash(dh, Uh, xh, 0)
+                res[nt_] = time.perf_counter() - t0
+            oracle.set_threads(nthr)
+            vhh = int(np.prod(dh)) // 2
+            emit({"suite": "oracle_hop", "dims": dh, "s_1_thread": round(res[1], 4), "s_all": round(res[nthr], 4),
+                  "threads": nthr, "GFLOPs_all": round(570 * vhh / res[nthr] / 1e9, 3),
+                  "model_GBps_all": round(1584 * vhh / res[nthr] / 1e9, 3)})
+            del Uh, xh
+        U4 = synth.gauge((4, 4, 4, 4), "haar", seed=1000)
+        b4 = synth.source((4, 4, 4, 4), 0, seed=2000)
+        t0 = time.perf_counter()
+        _, st4, it4, tr4 = oracle.cg((4, 4, 4, 4), U4, 0.1, b4, tol=TOL)
+        emit({"suite": "oracle_cg_4x4", "s": round(time.perf_counter() - t0, 4), "iters": it4, "true_res": tr4,
+              "threads": nthr})
 
     # 8. HMC on 24^4 (beta 5.5, m 0.05, tau 1): the plaquette force kernel alone, and whole
     #    trajectories with FP64 and mixed-precision solves (warm-started), Omelyan, 10 steps
-    Ud = torch.from_numpy(synth.gauge(dims, "smooth", seed=1004, eps=0.2)).to(dev)
-    Qd = torch.from_numpy(synth.momenta(dims, seed=3005)).to(dev)
-    vol = int(np.prod(dims))
-    Fd = torch.empty_like(Qd)
-    ms = event_ms(lambda: lqs.gauge_force(ctx, dims, Ud, 5.5, 1.0, out=Fd, accumulate=True), 10)
-    links = 4 * vol
-    # minimum traffic: every link read once, the momentum read and written (144 B each)
-    emit({"suite": "gauge_force_24x4", "ms": round(ms, 4), "links": links,
-          "min_GBps": round(links * 3 * 144 / ms / 1e6, 1),
-          "GFLOPs_fp64": round(links * (25 * 198 + 60) / ms / 1e6, 1),
-          "note": "per link 24 SU(3) products for the 6 staples + U V (198 flop each) + TA"})
-    eta = torch.from_numpy(synth.source(dims, -1, seed=3006) / np.sqrt(2)).to(dev)
-    for inner, recon in (("f64", 18), ("f32", 12), ("f16", 12)):
-        res = []
-        for k in range(2):
-            U0 = Ud.clone()
-            Q0 = torch.from_numpy(synth.momenta(dims, seed=3010 + k)).to(dev)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = lqs.hmc_trajectory(ctx, dims, U0, Q0, eta, u=0.5, beta=5.5, mass=0.05, tau=1.0, nsteps=10,
-                                    integrator=lqs.OMELYAN, fermions=1, tol=1e-10, inner_prec=lqs.PREC[inner],
-                                    inner_recon=recon, use_x0=True)
-            torch.cuda.synchronize()
-            res.append((time.perf_counter() - t0, st))
-        t_, st = res[-1]
-        emit({"suite": "hmc_24x4", "inner": inner, "recon": recon, "s_per_trajectory": round(t_, 4),
-              "cg_solves": st["cg_solves"], "cg_iters": st["cg_iters"], "dH": st["dH"],
-              "plaquette": st["plaquette"], "status": st["status"],
-              "note": "Omelyan, 10 steps, tau 1, beta 5.5, m 0.05, solves to 1e-10 warm-started"})
+    if want("hmc"):
+        dims = (24, 24, 24, 24)
+        Ud = torch.from_numpy(synth.gauge(dims, "smooth", seed=1004, eps=0.2)).to(dev)
+        Qd = torch.from_numpy(synth.momenta(dims, seed=3005)).to(dev)
+        vol = int(np.prod(dims))
+        Fd = torch.empty_like(Qd)
+        ms = event_ms(lambda: lqs.gauge_force(ctx, dims, Ud, 5.5, 1.0, out=Fd, accumulate=True), 10)
+        links = 4 * vol
+        # minimum traffic: every link read once, the momentum read and written (144 B each)
+        emit({"suite": "gauge_force_24x4", "ms": round(ms, 4), "links": links,
+              "min_GBps": round(links * 3 * 144 / ms / 1e6, 1),
+              "GFLOPs_fp64": round(links * (13 * 198 + 40) / ms / 1e6, 1),
+              "note": "per link 12 SU(3) products for the 6 staples + U V (198 flop each) + TA"})
+        eta = torch.from_numpy(synth.source(dims, -1, seed=3006) / np.sqrt(2)).to(dev)
+        for inner, recon, ftol in (("f64", 18, 0.0), ("f32", 12, 0.0), ("f16", 12, 0.0), ("f16", 12, 1e-7)):
+            res = []
+            for k in range(2):
+                U0 = Ud.clone()
+                Q0 = torch.from_numpy(synth.momenta(dims, seed=3010 + k)).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = lqs.hmc_trajectory(ctx, dims, U0, Q0, eta, u=0.5, beta=5.5, mass=0.05, tau=1.0, nsteps=10,
+                                        integrator=lqs.OMELYAN, fermions=1, tol=1e-10, inner_prec=lqs.PREC[inner],
+                                        inner_recon=recon, use_x0=True, force_tol=ftol)
+                torch.cuda.synchronize()
+                res.append((time.perf_counter() - t0, st))
+            t_, st = res[-1]
+            emit({"suite": "hmc_24x4", "inner": inner, "recon": recon, "force_tol": ftol,
+                  "s_per_trajectory": round(t_, 4),
+                  "cg_solves": st["cg_solves"], "cg_iters": st["cg_iters"], "dH": st["dH"],
+                  "plaquette": st["plaquette"], "status": st["status"],
+                  "note": "Omelyan, 10 steps, tau 1, beta 5.5, m 0.05, solves to 1e-10 (force solves to "
+                          "force_tol if set), warm-started"})
 
 
 if __name__ == "__main__":

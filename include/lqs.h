@@ -280,6 +280,8 @@ typedef struct {
                         /* on the starting links; 2 pf = phi itself (even sites)       */
     lqs_cg_params cg;   /* the solves chi = M^-1 phi (use_x0: start from the previous  */
                         /* chi; persistent is ignored)                                 */
+    double force_tol;   /* tolerance of the solves that only feed the force (0: cg.tol);*/
+                        /* the solves for S_f at both ends always use cg.tol           */
 } lqs_hmc_params;
 
 typedef struct {

@@ -60,7 +60,7 @@ class LqsCgStats(ctypes.Structure):
 class LqsHmcParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("mass", ctypes.c_double), ("tau", ctypes.c_double),
                 ("nsteps", ctypes.c_int32), ("integrator", ctypes.c_int32), ("lam", ctypes.c_double),
-                ("fermions", ctypes.c_int32), ("cg", LqsCgParams)]
+                ("fermions", ctypes.c_int32), ("cg", LqsCgParams), ("force_tol", ctypes.c_double)]
 
 
 class LqsHmcStats(ctypes.Structure):
@@ -411,14 +411,15 @@ def kinetic_energy(ctx, dims, mom, stream=None):
 
 def hmc_trajectory(ctx, dims, links, mom, pf=None, u=0.5, beta=5.5, mass=0.1, tau=1.0, nsteps=10,
                    integrator=LEAPFROG, lam=0.0, fermions=1, tol=1e-10, max_iter=10000, inner_prec=F64,
-                   inner_recon=18, reliable_interval=0, reliable_delta=0.0, use_x0=False, proposal=None,
-                   phi_out=None, stream=None, check=True):
+                   inner_recon=18, reliable_interval=0, reliable_delta=0.0, use_x0=False, force_tol=0.0,
+                   proposal=None, phi_out=None, stream=None, check=True):
     """One HMC trajectory on complex128 links/momenta (updated in place); pf: eta (fermions=1) or phi
     (fermions=2) as a complex128 lex tensor (Nt, Nz, Ny, Nx, 3).  Returns the stats dict."""
     nx, ny, nz, nt = dims
     p = LqsHmcParams(float(beta), float(mass), float(tau), int(nsteps), int(integrator), float(lam), int(fermions),
                      LqsCgParams(float(tol), int(max_iter), PREC[inner_prec], int(inner_recon),
-                                 int(reliable_interval), float(reliable_delta), 1 if use_x0 else 0, 0))
+                                 int(reliable_interval), float(reliable_delta), 1 if use_x0 else 0, 0),
+                     float(force_tol))
     st = LqsHmcStats()
     pfp = None
     if fermions:

@@ -538,6 +538,7 @@ lqs_status hmc_trajectory(lqs_ctx *ctx, const int32_t dims[4], double *links, do
         LQS_REQUIRE(std::isfinite(p.lambda) && p.lambda >= 0 && p.lambda < 0.5, LQS_EINVAL,
                     "lambda must be in [0, 0.5)");
         LQS_REQUIRE(p.fermions >= 0 && p.fermions <= 2, LQS_EINVAL, "fermions must be 0, 1 or 2");
+        LQS_REQUIRE(std::isfinite(p.force_tol) && p.force_tol >= 0, LQS_EINVAL, "force_tol must be finite and >= 0");
         LQS_REQUIRE(u >= 0 && u < 1, LQS_EINVAL, "u must be in [0, 1)");
         if (proposal) {
             check_ptr(proposal, "proposal");

@@ -142,22 +142,25 @@ __global__ void __launch_bounds__(1024) hmc_finalize(const double *partials, int
     if (threadIdx.x == 0) out[slot] = scale * (offset + s);
 }
 
-// F_g = (beta/3) TA(U V) on link (x, mu); mode 0: out = coeff F_g, 1: out += coeff F_g
-__global__ void __launch_bounds__(HMC_BLOCK) gauge_force_kernel(Geom g, int vol, const double2 *U, double beta,
-                                                                double coeff, int mode, double2 *out)
+// F_g = (beta/3) TA(U V) on link (x, mu); mode 0: out = coeff F_g, 1: out += coeff F_g.
+// Three threads per link: thread slot k of a block handles the direction
+// nu_k != mu (its upper and lower staple, four SU(3) products), the three
+// staple sums meet in LDS, and the slot-0 wave forms U V and its traceless
+// anti-Hermitian part.  A block covers 64 consecutive sites of one mu (one
+// wave per slot), so every load of a wave is a contiguous run of links.
+constexpr int GF_SITES = 64;
+
+__global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int vol, const double2 *U, double beta,
+                                                                   double coeff, int mode, double2 *out)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double2 part[3][9][GF_SITES];
     const int mu = blockIdx.y;
-    if (x >= vol) return;
-    const int xm = nbr(g, x, mu, 1);
-    Mat v;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) v.e[i][j] = {0.0, 0.0};
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == mu) continue;
+    const int slot = threadIdx.x / GF_SITES, lane = threadIdx.x % GF_SITES;
+    const int x = blockIdx.x * GF_SITES + lane;
+    const bool valid = x < vol;
+    if (valid) {
+        const int nu = slot + (slot >= mu ? 1 : 0);
+        const int xm = nbr(g, x, mu, 1);
         // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
         const int xn = nbr(g, x, nu, 1);
         Mat a = mat_mul<false, true>(mat_load(link_at(U, vol, nu, xm)), mat_load(link_at(U, vol, mu, xn)));
@@ -169,8 +172,19 @@ __global__ void __launch_bounds__(HMC_BLOCK) gauge_force_kernel(Geom g, int vol,
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) v.e[i][j] = cadd(v.e[i][j], cadd(a.e[i][j], b.e[i][j]));
+            for (int j = 0; j < 3; ++j)
+                part[slot][3 * i + j][lane] = make_double2(a.e[i][j].re + b.e[i][j].re, a.e[i][j].im + b.e[i][j].im);
     }
+    __syncthreads();
+    if (slot != 0 || !valid) return;
+    Mat v;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double2 p0 = part[0][3 * i + j][lane], p1 = part[1][3 * i + j][lane], p2 = part[2][3 * i + j][lane];
+            v.e[i][j] = {(p0.x + p1.x) + p2.x, (p0.y + p1.y) + p2.y};
+        }
     const Mat w = mat_mul<false, false>(mat_load(link_at(U, vol, mu, x)), v);
     // TA(W) = (W - W^dag)/2 - tr(W - W^dag)/6
     Mat t;
@@ -298,8 +312,8 @@ void launch_gauge_force(const Geom &g, const double *U, double beta, double coef
                         hipStream_t s)
 {
     const int vol = 2 * g.vh;
-    dim3 grid((vol + HMC_BLOCK - 1) / HMC_BLOCK, 4);
-    hipLaunchKernelGGL(gauge_force_kernel, grid, dim3(HMC_BLOCK), 0, s, g, vol, (const double2 *)U, beta, coeff,
+    dim3 grid((vol + GF_SITES - 1) / GF_SITES, 4);
+    hipLaunchKernelGGL(gauge_force_kernel, grid, dim3(3 * GF_SITES), 0, s, g, vol, (const double2 *)U, beta, coeff,
                        accumulate ? 1 : 0, (double2 *)out);
     LQS_HIP(hipGetLastError());
 }
@@ -400,22 +414,25 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
             launch_field_unpack(g, lqs_field{phi, F64, 0, 1}, phi_out, s);
         }
     }
-    // chi = M^-1 phi on the current links (warm start from the previous chi if asked)
-    auto solve = [&]() {
+    // chi = M^-1 phi on the current links (warm start from the previous chi if
+    // asked); solves that only feed the force may use the looser force_tol
+    auto solve = [&](bool energy) {
         lqs_problem pb{&wg.g, prm.mass, 1, phi, chi};
         lqs_cg_stats cs{};
         if (!warm) LQS_HIP(hipMemsetAsync(chi, 0, f64, s));
         cgp.use_x0 = warm ? 1 : 0;
+        cgp.tol = (energy || prm.force_tol <= 0) ? prm.cg.tol : prm.force_tol;
         cg_solve_one(ctx, pb, cgp, &cs, s);
         ++cg_solves;
         cg_iters += cs.iters;
         if (cs.status != LQS_OK && (worst == LQS_OK || cs.status < worst)) worst = cs.status;
     };
-    // mom -= eps F / 2, the fermion part from chi on the current links
-    auto momentum = [&](double eps, bool have_chi) {
+    // mom -= eps F / 2, the fermion part from chi on the current links; the
+    // solve on the final links (last) also gives S_f at the end
+    auto momentum = [&](double eps, bool have_chi, bool last) {
         launch_gauge_force(g, U1, prm.beta, -0.5 * eps, 1, mom, s);
         if (!ferm) return;
-        if (!have_chi) solve();
+        if (!have_chi) solve(last);
         launch_hop_gated(g, L64, F64, 18, 0, 1, 1, chi, psx, nullptr, 0, sh, s);
         launch_force(g, L64, chi, chi, psx, psx, -0.5 * eps, 2, mom, s);
     };
@@ -428,7 +445,7 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     launch_kinetic(ctx, g, mom, scal, 0, s);
     launch_gauge_action(ctx, g, U1, prm.beta, scal, 1, s);
     if (ferm) {
-        solve();
+        solve(true);
         launch_field_dot(ctx, g, 1, phi, chi, scal + 8, s);
     }
 
@@ -436,22 +453,23 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     const double lam = prm.lambda > 0 ? prm.lambda : 0.1931833275037836;
     bool have_chi = ferm;  // chi belongs to the current links
     if (prm.integrator == LQS_LEAPFROG) {
-        momentum(0.5 * h, have_chi);
+        momentum(0.5 * h, have_chi, false);
         for (int k = 0; k < prm.nsteps; ++k) {
             links_step(h);
-            momentum(k == prm.nsteps - 1 ? 0.5 * h : h, false);
+            const bool last = k == prm.nsteps - 1;
+            momentum(last ? 0.5 * h : h, false, last);
         }
     } else {
         // consecutive lam*h updates at a step boundary act on the same links: merged
         double pending = lam * h;
         for (int k = 0; k < prm.nsteps; ++k) {
-            momentum(pending, k == 0 && have_chi);
+            momentum(pending, k == 0 && have_chi, false);
             links_step(0.5 * h);
-            momentum((1.0 - 2.0 * lam) * h, false);
+            momentum((1.0 - 2.0 * lam) * h, false, false);
             links_step(0.5 * h);
             pending = 2.0 * lam * h;
         }
-        momentum(lam * h, false);
+        momentum(lam * h, false, true);
     }
     // H at the end: chi is the solve on the final links (last momentum step)
     launch_kinetic(ctx, g, mom, scal, 3, s);

@@ -80,18 +80,19 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     import paper_2502_03249_amd as lqs
     src = tmp_path / "sz.c"
     src.write_text('#include "lqs.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lqs_field), sizeof(lqs_problem), '
+                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lqs_field), sizeof(lqs_problem), '
                    'sizeof(lqs_cg_params), sizeof(lqs_cg_stats), offsetof(lqs_cg_params, reliable_delta), '
                    'offsetof(lqs_cg_stats, true_rel_residual), sizeof(lqs_hmc_params), sizeof(lqs_hmc_stats), '
                    'offsetof(lqs_hmc_params, cg), offsetof(lqs_hmc_stats, plaquette), '
-                   'offsetof(lqs_hmc_params, fermions));return 0;}\n')
+                   'offsetof(lqs_hmc_params, fermions), offsetof(lqs_hmc_params, force_tol));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(lqs.LqsField), ctypes.sizeof(lqs.LqsProblem), ctypes.sizeof(lqs.LqsCgParams),
             ctypes.sizeof(lqs.LqsCgStats), lqs.LqsCgParams.reliable_delta.offset,
             lqs.LqsCgStats.true_rel_residual.offset, ctypes.sizeof(lqs.LqsHmcParams), ctypes.sizeof(lqs.LqsHmcStats),
-            lqs.LqsHmcParams.cg.offset, lqs.LqsHmcStats.plaquette.offset, lqs.LqsHmcParams.fermions.offset]
+            lqs.LqsHmcParams.cg.offset, lqs.LqsHmcStats.plaquette.offset, lqs.LqsHmcParams.fermions.offset,
+            lqs.LqsHmcParams.force_tol.offset]
     assert got == want
 
 

@@ -174,3 +174,23 @@ def test_invalid_arguments(ctx):
     with pytest.raises(lqs.LqsError) as e:
         lqs.hmc_trajectory(ctx, dims, U, U, pf=dev(_eta(dims, 1)), fermions=1)
     assert e.value.status == lqs.EINVAL
+
+
+def test_force_tolerance_only_loosens_force_solves(ctx):
+    """force_tol loosens the solves inside the trajectory; the S_f solves at both ends keep tol."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge(dims, "smooth", seed=321, eps=0.2)
+    Q = synth.momenta(dims, seed=322)
+    eta = _eta(dims, 323)
+    kw = dict(beta=5.5, mass=0.1, tau=0.3, nsteps=4, integrator=lqs.OMELYAN, tol=1e-11, use_x0=True)
+    tight, _, _, U1t, _ = _run(ctx, dims, U, Q, eta, 1, **kw)
+    loose, _, _, U1l, _ = _run(ctx, dims, U, Q, eta, 1, force_tol=1e-6, **kw)
+    assert tight["status"] == 0 and loose["status"] == 0
+    assert loose["cg_solves"] == tight["cg_solves"] and loose["cg_iters"] < tight["cg_iters"]
+    for k in ("k0", "sg0", "sf0"):
+        assert abs(loose[k] - tight[k]) <= 1e-9 * abs(tight[k])
+    # force errors of order kappa * 1e-6 move the end point slightly; S_f there is still exact
+    o = oracle.hmc(dims, U1l, np.zeros_like(Q), None, 0.1, 5.5, 1e-9, 1, fermions=True,
+                   phi=oracle.pseudofermion(dims, U, 0.1, eta), cg_tol=1e-12)
+    assert abs(loose["sf1"] - o["energies"][2]) <= 1e-8 * abs(o["energies"][2])
+    assert rel(U1l, U1t) <= 1e-4
