@@ -116,3 +116,21 @@ def test_cg_zero_source(ctx):
     b = np.zeros((4, 4, 4, 4, 3), np.complex128)
     x, st = _solve(ctx, dims, U, 0.1, b)
     assert st[0]["status"] == 0 and np.abs(x).max() == 0.0
+
+
+def test_cg_full_size_benchmark_solve(ctx):
+    """The timed solve at full size: 64^3 x 16, m = 0.01, FP16 12-real inner, reliable updates every
+    100 iterations; the oracle recomputes ||b - M x|| / ||b|| in FP64."""
+    dims, mass = (64, 64, 64, 16), 0.01
+    U = synth.gauge(dims, "smooth", seed=1002, eps=0.3)
+    b = synth.source(dims, 0, seed=2002)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xf = bf.like().zero_()
+    st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=lqs.F16, inner_recon=12,
+                      reliable_interval=100)
+    assert st[0]["status"] == 0
+    x = lex_of(ctx, xf)
+    tr = oracle.true_residual(dims, U, mass, b, x)
+    assert tr <= 1e-10
+    assert abs(tr - st[0]["true_rel_residual"]) <= 1e-12

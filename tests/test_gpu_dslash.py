@@ -137,3 +137,15 @@ def test_full_size_hop_64x16(ctx):
     for recon in (18, 12):
         got = lex_of(ctx, lqs.dslash_apply(ctx, g, x, recon=recon))
         assert rel(got, want) <= 1e-12
+
+
+def test_full_size_low_precision_hops_64x16(ctx):
+    """64^3 x 16: the FP16 12-real hop the timed solve runs, and FP32 12-real, against the oracle."""
+    dims = (64, 64, 64, 16)
+    U = synth.gauge(dims, "smooth", seed=1002, eps=0.3)
+    src = synth.source(dims, 1, seed=2002)
+    g = gauge(ctx, dims, U, lqs.fmt(lqs.F16, 12) | lqs.fmt(lqs.F32, 12))
+    want = oracle.dslash(dims, U, src, 0)
+    for prec, bound in ((lqs.F16, 4e-3), (lqs.F32, 2e-6)):
+        got = lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, src, 1, prec), recon=12))
+        assert rel(got, want) <= bound
