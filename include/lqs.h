@@ -112,6 +112,13 @@ void lqs_ctx_destroy(lqs_ctx *ctx);
  * format) key and cache the fastest, 0 = use built-in defaults (default). */
 lqs_status lqs_set_tuning(lqs_ctx *ctx, int32_t enable);
 
+/* HIP graphs for the multi-kernel CG: 1 (default) = each solve captures one
+ * round of iterations (8 iterations and their gated FP64 groups) into a
+ * graph on a side stream and replays it, which removes most of the launch
+ * cost on small lattices; 0 = launch every kernel.  Results are identical.
+ * Graphs are not used while hop profiling is on. */
+lqs_status lqs_set_graphs(lqs_ctx *ctx, int32_t enable);
+
 /* Pack a canonical link field into the formats of the `formats` bitmask
  * (LQS_FMT(LQS_F64, 18) is always added; LQS_TEMPORAL_GAUGE may be or-ed in).
  * `links` is read on `stream`; the call returns once packing has been

@@ -88,7 +88,7 @@ EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_cre
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
            "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
            "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal", "gauge_action", "gauge_force",
-           "link_update", "kinetic_energy", "hmc_trajectory"]
+           "link_update", "kinetic_energy", "hmc_trajectory", "lqs_set_graphs"]
 
 
 def lib():
@@ -105,6 +105,7 @@ def lib():
     L.lqs_ctx_destroy.argtypes = [vp]
     L.lqs_ctx_destroy.restype = None
     L.lqs_set_tuning.argtypes = [vp, i32]
+    L.lqs_set_graphs.argtypes = [vp, i32]
     L.lqs_gauge_create.argtypes = [vp, i32p, vp, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
     L.lqs_gauge_destroy.argtypes = [vp]
     L.lqs_gauge_destroy.restype = None
@@ -171,6 +172,9 @@ class Context:
 
     def set_tuning(self, enable):
         _check(lib().lqs_set_tuning(self.handle, 1 if enable else 0))
+
+    def set_graphs(self, enable):
+        _check(lib().lqs_set_graphs(self.handle, 1 if enable else 0))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -197,6 +197,14 @@ lqs_status lqs_set_tuning(lqs_ctx *ctx, int32_t enable)
     });
 }
 
+lqs_status lqs_set_graphs(lqs_ctx *ctx, int32_t enable)
+{
+    return guard([&] {
+        LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
+        ctx->graphs = enable != 0;
+    });
+}
+
 lqs_status lqs_field_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs, size_t *bytes)
 {
     return guard([&] {

@@ -566,6 +566,9 @@ struct CgRun {
     int inflight = 0, slot = 0;
     int64_t enqueued = 0, cap = 0;
     bool done = false;
+    bool use_graph = false;  // s is a side stream and graphs are on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     static constexpr int chunk = 4;       // iterations between FP64 groups
     static constexpr int poll_every = 2;  // chunks between state polls
 
@@ -578,6 +581,15 @@ struct CgRun {
     {
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+
+    // one round: poll_every chunks of iterations, each closed by the gated FP64 group
+    void round()
+    {
+        for (int c = 0; c < poll_every; ++c)
+            for (int i = 0; i < chunk; ++i) cg_iteration(ctx, gauge(), v, s, i == chunk - 1);
     }
     const Gauge &gauge() const { return *pb.gauge; }
 
@@ -635,13 +647,31 @@ struct CgRun {
         cap = (int64_t)prm.max_iter + 16 * chunk + 64;
     }
 
-    // queue poll_every chunks of iterations and an asynchronous poll of the state
+    // queue one round of iterations and an asynchronous poll of the state.
+    // With graphs the round is captured once (the kernels read their scalars
+    // and gates from the device state, so every replay is the same work) and
+    // replayed; the round holds no memset or host synchronisation.
     void enqueue()
     {
-        for (int c = 0; c < poll_every; ++c) {
-            for (int i = 0; i < chunk; ++i) cg_iteration(ctx, gauge(), v, s, i == chunk - 1);
-            enqueued += chunk;
+        if (use_graph) {
+            if (!exec) {
+                LQS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    round();
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(s, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                LQS_HIP(hipStreamEndCapture(s, &graph));
+                LQS_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            LQS_HIP(hipGraphLaunch(exec, s));
+        } else {
+            round();
         }
+        enqueued += chunk * poll_every;
         LQS_HIP(hipMemcpyAsync(hs[slot], v.state, sbytes, hipMemcpyDeviceToHost, s));
         LQS_HIP(hipEventRecord(ev[slot], s));
         ++inflight;
@@ -697,18 +727,46 @@ struct CgRun {
 
 void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
 {
-    CgRun run(ctx, pb, prm, stats, s, "", std::chrono::steady_clock::now());
-    run.setup();
+    // graphs are captured on a side stream (the caller's stream may be the
+    // null stream, which cannot be captured), forked from and joined into s
+    const bool graphs = ctx.graphs && !ctx.profiling;
+    hipStream_t rs = graphs ? ctx.side_stream(0) : s;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (graphs) {
+        LQS_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        LQS_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    }
+    auto cleanup = [&]() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    };
     try {
-        while (!run.done) {
-            run.enqueue();
-            run.check();
+        if (graphs) {
+            LQS_HIP(hipEventRecord(fork, s));
+            LQS_HIP(hipStreamWaitEvent(rs, fork, 0));
+        }
+        CgRun run(ctx, pb, prm, stats, rs, "", std::chrono::steady_clock::now());
+        run.use_graph = graphs;
+        run.setup();
+        try {
+            while (!run.done) {
+                run.enqueue();
+                run.check();
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(rs);
+            throw;
+        }
+        run.finish();
+        if (graphs) {
+            LQS_HIP(hipEventRecord(join, rs));
+            LQS_HIP(hipStreamWaitEvent(s, join, 0));
         }
     } catch (...) {
-        (void)hipStreamSynchronize(s);
+        cleanup();
         throw;
     }
-    run.finish();
+    cleanup();
 }
 
 // Problems of different sizes each get a side stream (forked from and joined
@@ -737,6 +795,7 @@ void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lq
         for (int i = 0; i < nprob; ++i) {
             runs.emplace_back(new CgRun(ctx, probs[i], prm, stats + off, ctx.side_stream(i % nside),
                                         "#" + std::to_string(i), t0));
+            runs.back()->use_graph = ctx.graphs && !ctx.profiling;
             off += probs[i].nrhs;
         }
         for (auto &r : runs) r->setup();

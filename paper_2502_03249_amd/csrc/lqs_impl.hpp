@@ -97,6 +97,7 @@ struct Ctx {
     hipDeviceProp_t prop{};
     int num_cu = 0;
     bool tuning = false;
+    bool graphs = true;  // capture CG iteration rounds into HIP graphs
     std::unique_ptr<Tuner> tuner;
     // workspace buffers by slot, grown on demand, freed with the context
     std::map<std::string, std::pair<void *, size_t>> ws;

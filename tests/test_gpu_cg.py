@@ -134,3 +134,31 @@ def test_cg_full_size_benchmark_solve(ctx):
     tr = oracle.true_residual(dims, U, mass, b, x)
     assert tr <= 1e-10
     assert abs(tr - st[0]["true_rel_residual"]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,recon,nrhs", [(lqs.F64, 18, 1), (lqs.F16, 12, 1), (lqs.F32, 12, 3)])
+def test_graph_replay_equals_eager(ctx, prec, recon, nrhs):
+    """Solves whose iteration rounds are captured once into a HIP graph and replayed (with the
+    host's polls and copies between the replays) give the same bits and iteration counts as
+    launching every kernel; a second solve in a row recaptures for its own buffers."""
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "smooth", seed=131, eps=0.3)
+    b = np.stack([synth.source(dims, 0, seed=1310 + k) for k in range(nrhs)])
+    g = gauge(ctx, dims, U)
+    out = {}
+    for graphs in (False, True):
+        ctx.set_graphs(graphs)
+        for rep in range(2):
+            bf = field(ctx, dims, b, 0)
+            xf = bf.like().zero_()
+            st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=prec, inner_recon=recon,
+                              reliable_interval=50)
+            assert all(s["status"] == 0 for s in st)
+            out[(graphs, rep)] = (lex_of(ctx, xf, squeeze=False), [s["iters"] for s in st])
+    ctx.set_graphs(True)
+    ref = out[(False, 0)]
+    for k, (x, its) in out.items():
+        assert its == ref[1], k
+        assert np.array_equal(x, ref[0]), k
+    for k in range(nrhs):
+        assert oracle.true_residual(dims, U, mass, b[k], ref[0][k]) <= 1e-10
