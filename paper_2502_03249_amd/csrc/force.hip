@@ -5,7 +5,7 @@
 //   y odd : Pi_{y,mu} = -eps_mu(y) [Y(y+mu) psi_X(y)^dag + X(y+mu) psi_Y(y)^dag]
 // mode 0 stores F = coeff * (-TA(U Pi)) (su(3)), mode 1 stores coeff * Pi^dag,
 // mode 2 adds coeff * (-TA(U Pi)) to out (a momentum update).
-// One thread per link; output in the canonical [4][V][3][3] complex layout.
+// Output in the canonical [4][V][3][3] complex layout.
 #include "lqs_impl.hpp"
 
 namespace lqs {
@@ -23,28 +23,42 @@ __device__ __forceinline__ void outer_add(Cx<double> (&m)[3][3], const V3<double
         }
 }
 
+// One thread per link (mu, x) in lexicographic site order, so that a wave
+// writes 64 consecutive 144-byte output records (a parity-split grid left
+// every other record to another block and halved the write efficiency).
+// The two parities use the same code with their operands selected by address.
 __global__ void __launch_bounds__(256) force_kernel(Geom g, LinkRef L, const char *X, const char *Y, const char *psx,
                                                     const char *psy, double coeff, int mode, double2 *out)
 {
-    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mu = blockIdx.y >> 1, parity = blockIdx.y & 1;
-    if (cb >= g.vh) return;
+    const int lex = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (lex >= 2 * g.vh) return;
+    int q = lex / g.n[0];
+    const int xc = lex - q * g.n[0];
+    const int y = q % g.n[1];
+    q /= g.n[1];
+    const int parity = (xc + y + q % g.n[2] + q / g.n[2]) & 1;
+    const int cb = lex >> 1;
     const Site s = decode(g, cb, parity);
     const double e = ((s.negf >> mu) & 1) ? -1.0 : 1.0;
     const int nb = s.fwd[mu];
+    // y even: Pi = e [psi_X(y+mu) Y(y)^dag + psi_Y(y+mu) X(y)^dag]
+    // y odd : Pi = -e [Y(y+mu) psi_X(y)^dag + X(y+mu) psi_Y(y)^dag]
+    const bool ev = parity == 0;
+    const char *a1 = ev ? psx : Y, *b1 = ev ? Y : psx, *a2 = ev ? psy : X, *b2 = ev ? X : psy;
     Cx<double> pi[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) pi[i][j] = {0.0, 0.0};
-    if (parity == 0) {
-        outer_add(pi, SpinorIO<F64>::load(psx, g.vh, nb), SpinorIO<F64>::load(Y, g.vh, cb), e);
-        outer_add(pi, SpinorIO<F64>::load(psy, g.vh, nb), SpinorIO<F64>::load(X, g.vh, cb), e);
-    } else {
-        outer_add(pi, SpinorIO<F64>::load(Y, g.vh, nb), SpinorIO<F64>::load(psx, g.vh, cb), -e);
-        outer_add(pi, SpinorIO<F64>::load(X, g.vh, nb), SpinorIO<F64>::load(psy, g.vh, cb), -e);
-    }
-    double2 *o = out + 9 * ((int64_t)mu * 2 * g.vh + s.lex);
+    outer_add(pi, SpinorIO<F64>::load(a1, g.vh, nb), SpinorIO<F64>::load(b1, g.vh, cb), ev ? e : -e);
+    outer_add(pi, SpinorIO<F64>::load(a2, g.vh, nb), SpinorIO<F64>::load(b2, g.vh, cb), ev ? e : -e);
+    double2 *o = out + 9 * ((int64_t)mu * 2 * g.vh + lex);
+    // accumulate mode: fetch the old record up front, so that its loads overlap
+    // the arithmetic instead of alternating with the stores
+    double2 prev[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) prev[k] = mode == 2 ? o[k] : make_double2(0.0, 0.0);
     if (mode == 1) {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -76,20 +90,14 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, LinkRef L, const cha
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            double2 r = make_double2(-coeff * ta[i][j].re, -coeff * ta[i][j].im);
-            if (mode == 2) {
-                const double2 p = o[3 * i + j];
-                r.x += p.x;
-                r.y += p.y;
-            }
-            o[3 * i + j] = r;
+            o[3 * i + j] = make_double2(prev[3 * i + j].x - coeff * ta[i][j].re, prev[3 * i + j].y - coeff * ta[i][j].im);
         }
 }
 
 void launch_force(const Geom &g, LinkRef links64, const double *X, const double *Y, const double *psx,
                   const double *psy, double coeff, int mode, double *out, hipStream_t s)
 {
-    dim3 grid((g.vh + 255) / 256, 8);
+    dim3 grid((2 * g.vh + 255) / 256, 4);
     hipLaunchKernelGGL(force_kernel, grid, dim3(256), 0, s, g, links64, (const char *)X, (const char *)Y,
                        (const char *)psx, (const char *)psy, coeff, mode, (double2 *)out);
     LQS_HIP(hipGetLastError());

@@ -177,6 +177,11 @@ __global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int v
     }
     __syncthreads();
     if (slot != 0 || !valid) return;
+    double2 *o = out + 9 * ((int64_t)mu * vol + x);
+    // accumulate mode: fetch the old record before the arithmetic (see force.hip)
+    double2 prev[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) prev[k] = mode == 1 ? o[k] : make_double2(0.0, 0.0);
     Mat v;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -196,19 +201,11 @@ __global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int v
 #pragma unroll
     for (int i = 0; i < 3; ++i) t.e[i][i].im -= tri;
     const double c = coeff * beta / 3.0;
-    double2 *o = out + 9 * ((int64_t)mu * vol + x);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double2 r = make_double2(c * t.e[i][j].re, c * t.e[i][j].im);
-            if (mode == 1) {
-                const double2 p = o[3 * i + j];
-                r.x += p.x;
-                r.y += p.y;
-            }
-            o[3 * i + j] = r;
-        }
+        for (int j = 0; j < 3; ++j)
+            o[3 * i + j] = make_double2(prev[3 * i + j].x + c * t.e[i][j].re, prev[3 * i + j].y + c * t.e[i][j].im);
 }
 
 // exp(A) for a 3x3 complex A: A is scaled by 2^-s so that its max-row-sum
