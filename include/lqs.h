@@ -286,7 +286,8 @@ typedef struct {
     int32_t fermions;   /* 0 pure gauge; 1 pf = eta, phi = m eta_e - D_eo eta_o made   */
                         /* on the starting links; 2 pf = phi itself (even sites)       */
     lqs_cg_params cg;   /* the solves chi = M^-1 phi (use_x0: start from the previous  */
-                        /* chi; persistent is ignored)                                 */
+                        /* chi, from the third solve on from its linear extrapolation  */
+                        /* 2 chi_n - chi_(n-1); persistent is ignored)                 */
     double force_tol;   /* tolerance of the solves that only feed the force (0: cg.tol);*/
                         /* the solves for S_f at both ends always use cg.tol           */
 } lqs_hmc_params;

@@ -274,6 +274,18 @@ __global__ void __launch_bounds__(HMC_BLOCK) pseudofermion_kernel(int vh, double
     phi[i] = make_double2(m * a.x - b.x, m * a.y - b.y);
 }
 
+// Start of the next solve from the last two solutions (linear extrapolation in
+// molecular-dynamics time; successive solves are equally spaced, h/2 apart
+// for Omelyan and h for leapfrog): c <- 2c - p, p <- c.
+__global__ void __launch_bounds__(HMC_BLOCK) extrapolate_kernel(int64_t n, double2 *c, double2 *p)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 cv = c[i], pv = p[i];
+    p[i] = cv;
+    c[i] = make_double2(2.0 * cv.x - pv.x, 2.0 * cv.y - pv.y);
+}
+
 static int reduce_blocks(int64_t n)
 {
     int64_t b = (n + HMC_BLOCK - 1) / HMC_BLOCK;
@@ -383,7 +395,7 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     const LinkRef L64 = gauge.ref(F64, 18);
     const LaunchShape sh = default_hop_shape(L64, 1);
 
-    double *phi = nullptr, *chi = nullptr, *psx = nullptr;
+    double *phi = nullptr, *chi = nullptr, *psx = nullptr, *chi_prev = nullptr;
     int cg_solves = 0, cg_iters = 0, worst = LQS_OK;
     lqs_cg_params cgp = prm.cg;
     cgp.persistent = 0;
@@ -391,6 +403,7 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     if (ferm) {
         phi = (double *)ctx.workspace("hmc.phi", f64);
         chi = (double *)ctx.workspace("hmc.chi", f64);
+        chi_prev = (double *)ctx.workspace("hmc.chi_prev", f64);
         psx = (double *)ctx.workspace("hmc.psx", f64);
         LQS_HIP(hipMemsetAsync(chi, 0, f64, s));
         if (prm.fermions == 1) {
@@ -413,10 +426,21 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     }
     // chi = M^-1 phi on the current links (warm start from the previous chi if
     // asked); solves that only feed the force may use the looser force_tol
+    int nsol = 0;
     auto solve = [&](bool energy) {
         lqs_problem pb{&wg.g, prm.mass, 1, phi, chi};
         lqs_cg_stats cs{};
-        if (!warm) LQS_HIP(hipMemsetAsync(chi, 0, f64, s));
+        if (!warm) {
+            LQS_HIP(hipMemsetAsync(chi, 0, f64, s));
+        } else if (nsol == 1) {
+            LQS_HIP(hipMemcpyAsync(chi_prev, chi, f64, hipMemcpyDeviceToDevice, s));
+        } else if (nsol >= 2) {
+            const int64_t n = 3 * (int64_t)g.vh;
+            hipLaunchKernelGGL(extrapolate_kernel, dim3((unsigned)((n + HMC_BLOCK - 1) / HMC_BLOCK)), dim3(HMC_BLOCK), 0,
+                               s, n, (double2 *)chi, (double2 *)chi_prev);
+            LQS_HIP(hipGetLastError());
+        }
+        ++nsol;
         cgp.use_x0 = warm ? 1 : 0;
         cgp.tol = (energy || prm.force_tol <= 0) ? prm.cg.tol : prm.force_tol;
         cg_solve_one(ctx, pb, cgp, &cs, s);
