@@ -27,9 +27,12 @@ namespace lqs {
 
 static constexpr int BLAS_BLOCK = 256;
 static constexpr int MIN_HOP_BLOCK = 64;
+// largest number of <p,q> partials the update kernel sums in every block
+// (measured: folding pays on 32^4 and below, not on 64^3 x 16 with 8192)
+static constexpr int FOLD_ALPHA_MAX = 2048;
 
 // ---------------------------------------------------------------------------
-// scalar bookkeeping, run by one thread of the last block of a reduction
+// scalar bookkeeping, run by one thread of a one-block finalize kernel
 
 __device__ void fin_alpha(CgState &S, double pq)
 {
@@ -148,18 +151,42 @@ __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, cons
 }
 
 // ---------------------------------------------------------------------------
-// 3. x_lo += alpha p, r -= alpha q, |r|^2   (grid-stride, blockIdx.y = rhs)
+// 3. alpha = rho / <p, q>; x_lo += alpha p, r -= alpha q, |r|^2
+//    (grid-stride, blockIdx.y = rhs)
+//
+// With nd_blocks > 0 every block sums the normal kernel's <p, q> partials
+// itself, in the same order, so all blocks hold the same alpha without a
+// separate reduction kernel (used while the partials are few; beyond
+// FOLD_ALPHA_MAX of them the redundant sums cost more than the finalize
+// kernel they replace, and FIN_DOT sets alpha instead).  Within this kernel
+// no block reads a state field that another block writes: rho and phase are
+// read, block 0 writes alpha and, on a breakdown (which every block detects
+// by itself), the phase.
 
 template <int PA, int PI>
 __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, char *r, const char *p, const char *q,
-                                                            int64_t sa, int64_t si, CgState *st, double *partials,
-                                                            int max_blocks)
+                                                            int64_t sa, int64_t si, CgState *st,
+                                                            const double *pq_partials, int nd_blocks,
+                                                            double *partials, int max_blocks)
 {
     typedef typename RealOf<PA>::type T;
     const int rhs = blockIdx.y;
     CgState &S = st[rhs];
     if (S.phase != CG_RUNNING) return;
-    const T alpha = (T)S.alpha;
+    double alpha_d = S.alpha;  // nd_blocks == 0: set by the FIN_DOT finalize
+    if (nd_blocks > 0) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nd_blocks; i += blockDim.x) acc += pq_partials[(int64_t)rhs * max_blocks + i];
+        const double pq = block_sum(acc);
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (!isfinite(pq) || !(pq > 0.0)) {
+            if (lead) S.phase = isfinite(pq) ? CG_BREAKDOWN : CG_NONFINITE;
+            return;
+        }
+        alpha_d = S.rho / pq;
+        if (lead) S.alpha = alpha_d;
+    }
+    const T alpha = (T)alpha_d;
     x += rhs * sa;
     r += rhs * sa;
     p += rhs * si;
@@ -357,10 +384,11 @@ __global__ void __launch_bounds__(1024) finalize_kernel(CgState *st, const doubl
     }
 }
 
-static void launch_finalize(const CgVectors &v, int nblocks, int mode, int gate_mode, int sub, hipStream_t s)
+static void launch_finalize(const CgVectors &v, const double *partials, int nblocks, int mode, int gate_mode, int sub,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(v.nrhs), dim3(1024), 0, s, v.state, (const double *)v.partials,
-                       v.max_blocks, nblocks, mode, gate_mode, sub);
+    hipLaunchKernelGGL(finalize_kernel, dim3(v.nrhs), dim3(1024), 0, s, v.state, partials, v.max_blocks, nblocks,
+                       mode, gate_mode, sub);
     LQS_HIP(hipGetLastError());
 }
 
@@ -421,19 +449,24 @@ void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape
     else launch_normal_dot<F16, 12>(gauge, v, shd, s);
 }
 
-template <int PA, int PI> static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, hipStream_t s)
+// which 0: update (alpha from the nd_blocks <p,q> partials in v.partials, or
+// from the state when nd_blocks is 0; |r|^2 partials into v.partials2) and
+// its finalize; 1: p = r + beta p
+template <int PA, int PI>
+static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, int nd_blocks, hipStream_t s)
 {
     const int vh = (int)gauge.vh;
     const int64_t sa = field_bytes(gauge.g, PA, 1), si = field_bytes(gauge.g, PI, 1);
     dim3 grid(blas_blocks(vh), v.nrhs);
     if (which == 0)
         hipLaunchKernelGGL((update_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.xlo, (char *)v.r,
-                           (const char *)v.p, (const char *)v.q, sa, si, v.state, v.partials, v.max_blocks);
+                           (const char *)v.p, (const char *)v.q, sa, si, v.state, (const double *)v.partials,
+                           nd_blocks, v.partials2, v.max_blocks);
     else
         hipLaunchKernelGGL((pupdate_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (const char *)v.r,
                            (char *)v.p, sa, si, (const CgState *)v.state);
     LQS_HIP(hipGetLastError());
-    if (which == 0) launch_finalize(v, grid.x, FIN_UPDATE, 0, 0, s);
+    if (which == 0) launch_finalize(v, v.partials2, grid.x, FIN_UPDATE, 0, 0, s);
 }
 
 template <int PA>
@@ -456,7 +489,7 @@ static void launch_residual_t(const Gauge &gauge, const CgVectors &v, int gate_m
                            (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
                            gate_mode, mode);
     LQS_HIP(hipGetLastError());
-    launch_finalize(v, grid.x, FIN_RESID, gate_mode, mode, s);
+    launch_finalize(v, v.partials, grid.x, FIN_RESID, gate_mode, mode, s);
 }
 
 static void launch_residual(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
@@ -502,7 +535,7 @@ void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_
     else LQS_INIT(F32, F16);
 #undef LQS_INIT
     LQS_HIP(hipGetLastError());
-    launch_finalize(v, grid.x, FIN_INIT, 0, cold, s);
+    launch_finalize(v, v.partials, grid.x, FIN_INIT, 0, cold, s);
     if (use_x0) {
         cg_residual_group(ctx, gauge, v, 0, 1, s);
         launch_convert(gauge.g, v.nrhs, v.acc_prec, v.r, v.prec, v.p, s);
@@ -524,17 +557,21 @@ void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, boo
     prof_end(ctx, v.prec, v.recon, gauge.vh * v.nrhs, s);
     // 2. q = m^2 p - D_eo t, <p,q>
     launch_normal_dot_shape(gauge, v, shd, s);
-    launch_finalize(v, (int)((gauge.vh + shd.block - 1) / shd.block), FIN_DOT, 0, 0, s);
     // 3. update
-    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 0, s);
-    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, s);
-    else launch_blas<F32, F16>(gauge, v, 0, s);
+    int nd_blocks = (int)((gauge.vh + shd.block - 1) / shd.block);
+    if (nd_blocks > FOLD_ALPHA_MAX) {
+        launch_finalize(v, v.partials, nd_blocks, FIN_DOT, 0, 0, s);
+        nd_blocks = 0;
+    }
+    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 0, nd_blocks, s);
+    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, nd_blocks, s);
+    else launch_blas<F32, F16>(gauge, v, 0, nd_blocks, s);
     // FP64 residual group (gated)
     if (with_reliable) cg_residual_group(ctx, gauge, v, 2, 0, s);
     // 4. p = r + beta p
-    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 1, s);
-    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 1, s);
-    else launch_blas<F32, F16>(gauge, v, 1, s);
+    if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 1, 0, s);
+    else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 1, 0, s);
+    else launch_blas<F32, F16>(gauge, v, 1, 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,6 +661,7 @@ struct CgRun {
         }
         v.max_blocks = cg_partials_needed(gauge(), nrhs);
         v.partials = (double *)ctx.workspace("cg.partials" + tag, sizeof(double) * (size_t)v.max_blocks * nrhs);
+        v.partials2 = (double *)ctx.workspace("cg.partials2" + tag, sizeof(double) * (size_t)v.max_blocks * nrhs);
         v.state = (CgState *)ctx.workspace("cg.state" + tag, sizeof(CgState) * nrhs);
         sbytes = sizeof(CgState) * nrhs;
         char *host = (char *)ctx.pinned("cg.host" + tag, 2 * sbytes);

@@ -189,7 +189,8 @@ struct CgVectors {
     double *x, *b, *rhi;    // FP64: solution, source, FP64 residual (even)
     void *t64;              // FP64 odd scratch (residual hop)
     CgState *state;         // nrhs records
-    double *partials;       // nrhs * max_blocks
+    double *partials;       // nrhs * max_blocks (normal kernel, residual, init)
+    double *partials2;      // nrhs * max_blocks (update kernel)
     int max_blocks;
 };
 void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_t s);
