@@ -483,6 +483,35 @@ def run_suite(a):
         for g_, _, _, _ in probs:
             g_.close()
 
+    # 4b. many small lattices: 64 lattices of 4^4 / 4^3x6 / 6x4^3 (m 0.1 .. 0.73), one persistent launch
+    #     (one block per lattice) vs one multi-kernel call (side streams) vs one call per lattice
+    if want("uneven"):
+        shapes = [(4, 4, 4, 4), (4, 4, 4, 6), (6, 4, 4, 4)]
+        probs = []
+        for k in range(64):
+            _, g_, b_ = setup(shapes[k % 3], "smooth", 1300 + k, [2300 + k])
+            probs.append((g_, 0.1 + 0.01 * k, b_, b_.like()))
+        for prec in ("f64", "f16"):
+            pr = lqs.PREC[prec]
+            st = []
+            tp = timed(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
+                                                      tol=TOL, inner_prec=pr, reliable_interval=100,
+                                                      persistent=True)), 3)
+            tc = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
+                                            inner_prec=pr, reliable_interval=100), 3)
+
+            def sequential():
+                for g_, m_, b_, x_ in probs:
+                    lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_())], tol=TOL, inner_prec=pr, reliable_interval=100)
+            tq = timed(sequential, 1)
+            emit({"suite": "many_small_batch", "lattices": 64, "shapes": shapes, "inner": prec,
+                  "persistent_s": round(tp, 5), "concurrent_multikernel_s": round(tc, 5), "sequential_s": round(tq, 5),
+                  "persistent_vs_sequential": round(tq / tp, 2), "persistent_vs_concurrent": round(tc / tp, 2),
+                  "max_iters": max(r["iters"] for r in st[-1]),
+                  "all_converged": all(r["status"] == 0 for r in st[-1])})
+        for g_, _, _, _ in probs:
+            g_.close()
+
     # 5. small-lattice and 32^3x8 FP64 CG (multi-kernel and persistent)
     if want("small_cg"):
         for dims, kind, ls, ss, mass in [((4, 4, 4, 4), "haar", 1000, 2000, 0.1), ((32, 32, 32, 8), "smooth", 1001, 2001, 0.02)]:

@@ -207,9 +207,13 @@ typedef struct {
 
 /* Solve nprob systems.  stats receives one entry per (problem, right-hand
  * side), in order.  Returns the worst status.  The solve runs on `stream`
- * and the call returns when it has finished.  persistent = 1 requires
- * nrhs == 1 for every problem and a context whose device supports
- * cooperative launches (else LQS_EUNSUPPORTED). */
+ * and the call returns when it has finished.  With persistent = 0 several
+ * problems run concurrently on side streams.  persistent = 1 runs them all
+ * in one cooperative launch, one block group per lattice; it requires
+ * nrhs == 1 for every problem, use_x0 = 0, at most 256 problems and no more
+ * than the device's resident blocks, and cooperative launch support (else
+ * LQS_EUNSUPPORTED).  It pays off for small lattices, whose group is a
+ * single block. */
 lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const lqs_cg_params *params,
                     lqs_cg_stats *stats, void *stream);
 

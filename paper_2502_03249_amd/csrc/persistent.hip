@@ -28,7 +28,7 @@
 
 namespace lqs {
 
-static constexpr int PMAX_LAT = 8;
+static constexpr int PMAX_LAT = 256;
 
 struct PLat {
     Geom g;
@@ -389,7 +389,7 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
 {
     auto t0 = std::chrono::steady_clock::now();
     const int nlat = (int)probs.size();
-    LQS_REQUIRE(nlat >= 1 && nlat <= PMAX_LAT, LQS_EUNSUPPORTED, "persistent solve takes 1..8 lattices");
+    LQS_REQUIRE(nlat >= 1 && nlat <= PMAX_LAT, LQS_EUNSUPPORTED, "persistent solve takes 1..256 lattices");
     LQS_REQUIRE(!prm.use_x0, LQS_EUNSUPPORTED, "persistent solve starts from x = 0");
     int coop = 0;
     LQS_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx.device));

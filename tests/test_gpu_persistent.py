@@ -135,3 +135,18 @@ def test_concurrent_many_small_problems_share_streams(ctx):
     for k in range(4):
         assert st[9 + k]["status"] == 0
         assert oracle.true_residual(dims4, U4, 0.2, b4[k], x4[k]) <= 1e-10
+
+
+def test_persistent_many_small_lattices(ctx):
+    """Forty small lattices of three shapes in one launch, each in its own one-block group."""
+    shapes = [(4, 4, 4, 4), (4, 4, 4, 6), (4, 6, 4, 4)]
+    specs = [(shapes[k % 3], 0.1 + 0.01 * k, 1200 + k, 2200 + k) for k in range(40)]
+    probs, host = _setup(ctx, specs)
+    for prec in (lqs.F64, lqs.F16):
+        for _, _, _, xf in probs:
+            xf.zero_()
+        st = lqs.cg_solve(ctx, probs, tol=1e-10, inner_prec=prec, reliable_interval=100, persistent=True)
+        assert len(st) == 40
+        for (g, mass, bf, xf), (dims, U, m, b), s in zip(probs, host, st):
+            assert s["status"] == 0, s
+            assert oracle.true_residual(dims, U, m, b, lex_of(ctx, xf)) <= 1e-10
