@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--hop-reps", type=int, default=20)
     ap.add_argument("--only-hop", default=None, help="prec:recon, e.g. f64:18 -- hop launches only (profiling)")
     ap.add_argument("--only-copy", action="store_true", help="plain copy kernel only (counter calibration)")
+    ap.add_argument("--hop-nrhs", type=int, default=1, help="right-hand sides of the --only-hop launches")
     ap.add_argument("--dims", default=None, help="override lattice, e.g. 32,32,32,8")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads (size sweep, multi-RHS, batches, force); one JSON line each")
@@ -134,10 +135,12 @@ def main():
     setup_s = time.time() - t_setup
     vh = int(np.prod(dims)) // 2
 
-    def hop_rate(prec, recon, reps):
-        """Standalone hop D_eo on a random odd field; HIP events on the launch stream."""
+    def hop_rate(prec, recon, reps, nrhs=1):
+        """Standalone hop D_eo on nrhs random odd fields; HIP events on the launch stream."""
         pr = lqs.PREC[prec]
-        xin = lqs.Field.from_lex(ctx, torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev), 1, pr)
+        src = synth.source(dims, 1, seed=7) if nrhs == 1 else \
+            np.stack([synth.source(dims, 1, seed=7 + k) for k in range(nrhs)])
+        xin = lqs.Field.from_lex(ctx, torch.from_numpy(src).to(dev), 1, pr)
         out = xin.like(parity=0)
         for _ in range(3):
             lqs.dslash_apply(ctx, g, xin, out, recon=recon)
@@ -147,17 +150,20 @@ def main():
         torch.cuda.synchronize()
         n, ms, sites = lqs.profile_hops_result(ctx, pr, recon)
         lqs.profile_hops(ctx, False)
-        mb = model.hop_model_bytes(pr, recon) * vh
-        nb = model.hop_min_bytes(pr, recon) * vh
-        return {"prec": prec, "recon": recon, "ms": ms, "model_GBps": mb / ms / 1e6, "min_GBps": nb / ms / 1e6,
-                "frac_hbm_min": nb / ms / 1e6 / PEAK_HBM_GBPS,
-                "GFLOPs": model.FLOPS_PER_SITE * vh / ms / 1e6, "frac_hbm": mb / ms / 1e6 / PEAK_HBM_GBPS,
-                "model_bytes_per_site": model.hop_model_bytes(pr, recon),
-                "min_bytes_per_site": model.hop_min_bytes(pr, recon), "launches": n}
+        mb = model.hop_model_bytes(pr, recon, nrhs) * vh
+        nb = model.hop_min_bytes(pr, recon, nrhs) * vh
+        r = {"prec": prec, "recon": recon, "ms": ms, "model_GBps": mb / ms / 1e6, "min_GBps": nb / ms / 1e6,
+             "frac_hbm_min": nb / ms / 1e6 / PEAK_HBM_GBPS,
+             "GFLOPs": model.FLOPS_PER_SITE * nrhs * vh / ms / 1e6, "frac_hbm": mb / ms / 1e6 / PEAK_HBM_GBPS,
+             "model_bytes_per_site": model.hop_model_bytes(pr, recon, nrhs),
+             "min_bytes_per_site": model.hop_min_bytes(pr, recon, nrhs), "launches": n}
+        if nrhs > 1:
+            r["nrhs"] = nrhs
+        return r
 
     if a.only_hop:
         prec, recon = a.only_hop.split(":")
-        r = hop_rate(prec, int(recon), a.hop_reps)
+        r = hop_rate(prec, int(recon), a.hop_reps, a.hop_nrhs)
         print(json.dumps(r))
         return
 

@@ -103,11 +103,11 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 template <int P, int R, int K, int LF>
 __global__ void __launch_bounds__(512) normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, double m2, CgState *st, double *partials,
-                                                         int max_blocks, int nrhs, int ngroups)
+                                                         int max_blocks, int nrhs, int ngroups, int tpx)
 {
     typedef typename RealOf<P>::type T;
     int tile, grp;
-    tile_group(ngroups, tile, grp);
+    tile_group(ngroups, tpx, tile, grp);
     if (tile * (int)blockDim.x >= g.vh) return;  // padding tile (whole block)
     const int cb = tile * blockDim.x + threadIdx.x;
     const bool valid = cb < g.vh;
@@ -418,11 +418,12 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     // the two-sided kernel with the second side inactive does not
     if (L.temporal && sh.rhs_per_thread == 1) sh.rhs_per_thread = 2;
     const int tiles = (g.vh + sh.block - 1) / sh.block, G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
-    const dim3 grid(tile_group_blocks(tiles, G));
+    const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
+    const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
     const double m2 = v.mass * v.mass;
 #define LQS_ND(K, LF)                                                                                             \
     hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
-                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G)
+                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G, tpx)
 #define LQS_ND_LF(LF)                                                                                            \
     if (sh.rhs_per_thread == 1) LQS_ND(1, LF);                                                                   \
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \

@@ -23,11 +23,11 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
 template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
-                                                  const CgState *gate, int gate_mode, int ngroups)
+                                                  const CgState *gate, int gate_mode, int ngroups, int tpx)
 {
     typedef typename RealOf<P>::type T;
     int tile, grp;
-    tile_group(ngroups, tile, grp);
+    tile_group(ngroups, tpx, tile, grp);
     const int cb = tile * blockDim.x + threadIdx.x;
     if (cb >= g.vh) return;
     const int r0 = grp * K;
@@ -60,11 +60,12 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
 {
     const int64_t stride = field_bytes(g, P, 1);
     const int tiles = (g.vh + sh.block - 1) / sh.block, G = (nrhs + K - 1) / K;
-    const dim3 grid(tile_group_blocks(tiles, G));
+    const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
+    const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
 #define LQS_HOP(DAG, LF)                                                                                         \
     hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), 0, s, g, L, parity, nrhs,            \
-                       (const char *)in, stride, (char *)out, stride, gate, gate_mode, G)
+                       (const char *)in, stride, (char *)out, stride, gate, gate_mode, G, tpx)
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
     else LQS_HOP(false, LF)

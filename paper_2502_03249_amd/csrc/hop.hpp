@@ -18,25 +18,39 @@ namespace lqs {
 // apart.
 enum { LF_TEMPORAL = 1, LF_STREAM = 2 };
 
-// Block -> (site tile, right-hand-side group) for launches over several
-// groups of right-hand sides.  The G blocks of one site tile are 8 block
-// indices apart: the round-robin dispatch over the 8 XCDs puts them on the
-// same XCD in close succession, so the links they share come from HBM once
-// and then from that XCD's L2.  The grid has ceil(tiles / 8) * 8 * G blocks;
-// tiles past the last are empty.  With G == 1 the map is the identity.
-__device__ __forceinline__ void tile_group(int G, int &tile, int &grp)
+// Block -> (site tile, right-hand-side group).  Consecutive block indices go
+// to the 8 XCDs in turn, each with its own L2; two maps build on that:
+//  - round robin (tpx == 0): tile t runs on XCD t mod 8, and the G blocks of
+//    one tile are 8 block indices apart, so they run on the same XCD in close
+//    succession and the links they share come from HBM once, then from that
+//    XCD's L2.  Neighbour tiles a multiple of 8 tiles away share the XCD.
+//  - slab (tpx > 0): XCD x sweeps the contiguous tiles [x tpx, (x + 1) tpx),
+//    so every neighbour except those across the slab ends is in its L2.
+// Both grids have ceil(tiles / 8) * 8 * G blocks (exactly `tiles` for the
+// round-robin map with G == 1, where it is the identity); tiles past the last
+// are empty.
+__device__ __forceinline__ void tile_group(int G, int tpx, int &tile, int &grp)
 {
-    if (G == 1) {
-        tile = blockIdx.x;
-        grp = 0;
-        return;
-    }
     const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
     grp = q % G;
-    tile = (q / G) * 8 + xcd;
+    tile = tpx ? xcd * tpx + q / G : (q / G) * 8 + xcd;
 }
 
-inline unsigned tile_group_blocks(int tiles, int G) { return G == 1 ? tiles : ((tiles + 7) / 8) * 8 * G; }
+inline unsigned tile_group_blocks(int tiles, int G, bool slab)
+{
+    return (G == 1 && !slab) ? tiles : ((tiles + 7) / 8) * 8 * G;
+}
+
+// The round-robin map keeps the z and t neighbours of a tile on its XCD when
+// the z stride (Nx Ny / 2 sites) is a whole number of 8-tile strides; the
+// slab map is used otherwise.
+inline bool xcd_slab_auto(const Geom &g, int block) { return ((int64_t)g.n[0] * g.n[1] / 2) % (8 * block) != 0; }
+inline int slab_tiles_per_xcd(const Geom &g, int block, int xcd_slab)
+{
+    const int tiles = (g.vh + block - 1) / block;
+    const bool slab = xcd_slab < 0 ? xcd_slab_auto(g, block) : xcd_slab != 0;
+    return slab ? (tiles + 7) / 8 : 0;
+}
 
 template <int P, int R, int K, int LF = 0>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,

@@ -2,16 +2,18 @@
 //
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
-// thread x cached or streaming link loads) with HIP events on the caller's
-// stream, keeps the one with the lowest median time, and stores it in a flat
-// JSON object {"key": "block,rhs_per_thread,stream_links", ...} that later
-// runs load.  Tuning runs
+// thread x cached or streaming link loads, then the other block -> XCD map
+// for the best of these) with HIP events on the caller's stream, keeps the
+// one with the lowest median time, and stores it in a flat JSON object
+// {"key": "block,rhs_per_thread,stream_links,xcd_slab", ...} that later runs
+// load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
 #include <cstring>
 #include <fstream>
 #include <sstream>
 
+#include "hop.hpp"
 #include "lqs_impl.hpp"
 
 namespace lqs {
@@ -42,25 +44,28 @@ Tuner::Tuner(const char *p)
 }
 
 // On a hit the stored fields replace those of `out`; an entry without the
-// third field keeps out.stream_links.
+// third or fourth field keeps out.stream_links or out.xcd_slab.
 bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) const
 {
     auto it = cache.find(key);
     if (it == cache.end()) return false;
-    int b = 0, k = 0, st = out.stream_links;
-    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d", &b, &k, &st);
+    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab;
+    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d", &b, &k, &st, &sl);
     if (n < 2) return false;
-    if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1)) return false;
+    if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1) ||
+        !(sl >= -1 && sl <= 1))
+        return false;
     out.block = b;
     out.rhs_per_thread = k;
     out.stream_links = st;
+    out.xcd_slab = sl;
     return true;
 }
 
 void Tuner::store(const std::string &key, const LaunchShape &v)
 {
     cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread) + "," +
-                 std::to_string(v.stream_links);
+                 std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab);
 }
 
 void Tuner::save() const
@@ -140,9 +145,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LQS_HIP(hipEventCreate(&e0));
     LQS_HIP(hipEventCreate(&e1));
     const LinkRef L = gauge.ref(prec, recon);
-    float best = 1e30f;
-    LaunchShape best_shape = default_hop_shape(L, nrhs);
-    for (const LaunchShape &c : candidates(nrhs)) {
+    auto time_shape = [&](const LaunchShape &c) {
         std::vector<float> t;
         for (int rep = 0; rep < 7; ++rep) {
             if (is_dot)
@@ -157,12 +160,21 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
             if (rep >= 2) t.push_back(ms);
         }
         std::sort(t.begin(), t.end());
-        const float med = t[t.size() / 2];
+        return t[t.size() / 2];
+    };
+    float best = 1e30f;
+    LaunchShape best_shape = default_hop_shape(L, nrhs);
+    for (const LaunchShape &c : candidates(nrhs)) {
+        const float med = time_shape(c);
         if (med < best) {
             best = med;
             best_shape = c;
         }
     }
+    // the candidates use the map the lattice shape selects; try the other
+    LaunchShape flip = best_shape;
+    flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
+    if (time_shape(flip) < best) best_shape = flip;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx.tuner->store(key, best_shape);

@@ -42,8 +42,8 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
     assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
     for v in entries.values():
-        blk, k, st = (int(t) for t in v.split(","))
-        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1)
+        blk, k, st, sl = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1)
 
     # the persistent multi-lattice solve tunes its resident blocks per compute unit
     tuned = lqs.Context(0, tune_cache=cache, tuning=True)
@@ -63,7 +63,7 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     entries = json.load(open(cache))
     pkeys = [k for k in entries if "|persistent|p1|r18|8x8x8x16|4x6x8x10" in k]
     assert len(pkeys) == 1
-    blk, bpc, _ = (int(t) for t in entries[pkeys[0]].split(","))
+    blk, bpc = (int(t) for t in entries[pkeys[0]].split(",")[:2])
     assert blk in (256, 512, 1024) and bpc in (1, 2, 4)
 
     # a new context loads the cache and does not need to tune again
@@ -126,3 +126,49 @@ def test_streaming_link_loads(tmp_path, prec, recon, bound):
     assert rel(out[0][0], out[1][0]) <= eps
     # both solutions satisfy ||x - x*|| <= kappa tol ||x*||, kappa <= (m^2 + 64) / m^2
     assert rel(out[0][1], out[1][1]) <= 2 * (mass ** 2 + 64) / mass ** 2 * 1e-10
+
+
+def test_xcd_maps_give_identical_results(tmp_path):
+    """Both block -> tile maps (round robin over the XCDs, one slab per XCD)
+    cover every (site tile, right-hand-side group) once: hops are bit-identical,
+    and so is a CG solve, whose <p, q> partials are indexed by tile."""
+    dims, mass = (6, 8, 10, 12), 0.07  # 2880 sites per parity: ragged tiles of 64
+    U = synth.gauge(dims, "haar", seed=95)
+    srcs = np.stack([synth.source(dims, 1, seed=950 + k) for k in range(3)])
+    b = synth.source(dims, 0, seed=96)
+    cache = str(tmp_path / "tune.json")
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    g = gauge(tuned, dims, U)
+    lqs.dslash_apply(tuned, g, field(tuned, dims, srcs, 1))
+    lqs.dslash_apply(tuned, g, field(tuned, dims, srcs[0], 1))
+    bf = field(tuned, dims, b, 0)
+    lqs.cg_solve(tuned, [(g, mass, bf, bf.like().zero_())], tol=1e-10, inner_prec=lqs.F32, reliable_interval=50)
+    tuned.close()
+    entries = json.load(open(cache))
+    keys = {n: [k for k in entries if f"|{n}|6x8x10x12|" in k] for n in ("hop", "normal_dot")}
+    assert len(keys["hop"]) >= 2 and keys["normal_dot"]
+
+    outs = []
+    for sl in (0, 1):
+        for k in keys["hop"]:
+            entries[k] = "64,1,0,%d" % sl if k.endswith("|n1") else "64,2,0,%d" % sl
+        for k in keys["normal_dot"]:
+            entries[k] = "64,1,0,%d" % sl
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        gg = gauge(ctx, dims, U)
+        h3 = lex_of(ctx, lqs.dslash_apply(ctx, gg, field(ctx, dims, srcs, 1)), squeeze=False)
+        h1 = lex_of(ctx, lqs.dslash_apply(ctx, gg, field(ctx, dims, srcs[0], 1)))
+        bb = field(ctx, dims, b, 0)
+        xx = bb.like().zero_()
+        st = lqs.cg_solve(ctx, [(gg, mass, bb, xx)], tol=1e-10, inner_prec=lqs.F32, reliable_interval=50)
+        assert st[0]["status"] == 0
+        x = lex_of(ctx, xx)
+        assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+        outs.append((h3, h1, x, st[0]["iters"]))
+        ctx.close()
+    (a3, a1, ax, ai), (b3, b1, bx, bi) = outs
+    assert np.array_equal(a3, b3) and np.array_equal(a1, b1)
+    assert ai == bi and np.array_equal(ax, bx)
+    assert rel(a1, oracle.dslash(dims, U, srcs[0], 0)) <= 1e-14
