@@ -85,9 +85,6 @@ Gauge::~Gauge()
     for (auto &row : fmt)
         for (auto &p : row)
             if (p) (void)hipFree(p);
-    for (auto &row : unit)
-        for (auto &p : row)
-            if (p) (void)hipFree(p);
 }
 
 }  // namespace lqs
@@ -237,17 +234,15 @@ lqs_status lqs_gauge_create(lqs_ctx *ctx, const int32_t dims[4], const double *l
             g->g = make_geom(dims);
             g->vh = g->g.vh;
             g->temporal = temporal;
+            g->pitch = temporal ? g->vh + TEMPORAL_PAD : g->vh;
             for (int prec = 0; prec < 3; ++prec)
                 for (int rc = 0; rc < 2; ++rc) {
                     const int recon = rc ? 12 : 18;
                     if (!(formats & LQS_FMT(prec, recon))) continue;
-                    const size_t bytes = (size_t)link_block_bytes_per_site(prec, recon) * g->vh * 8;
+                    const size_t bytes = (size_t)link_block_bytes_per_site(prec, recon) * g->pitch * 8;
                     LQS_HIP(hipMalloc(&g->fmt[prec][rc], bytes));
-                    launch_pack_links(g->g, links, prec, recon, g->fmt[prec][rc], as_stream(stream));
-                    if (temporal) {
-                        LQS_HIP(hipMalloc(&g->unit[prec][rc], 256));
-                        launch_unit_link(prec, recon, g->unit[prec][rc], as_stream(stream));
-                    }
+                    launch_pack_links(g->g, links, prec, recon, g->pitch, g->fmt[prec][rc], as_stream(stream));
+                    if (temporal) launch_unit_link(g->g, prec, recon, g->pitch, g->fmt[prec][rc], as_stream(stream));
                 }
         } catch (...) {
             delete g;

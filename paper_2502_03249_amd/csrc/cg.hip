@@ -414,9 +414,6 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const Geom &g = gauge.g;
     const int64_t stride = field_bytes(g, P, 1);
     const LinkRef L = gauge.ref(P, R);
-    // temporal gauge: one right-hand side per thread spills (as in the hop),
-    // the two-sided kernel with the second side inactive does not
-    if (L.temporal && sh.rhs_per_thread == 1) sh.rhs_per_thread = 2;
     const int tiles = (g.vh + sh.block - 1) / sh.block, G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
     const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
     const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));

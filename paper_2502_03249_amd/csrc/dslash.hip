@@ -84,11 +84,7 @@ template <int P, int R>
 static void launch_pr(const Geom &g, LinkRef L, int dagger, int parity, int nrhs, const void *in, void *out,
                       const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
-    // The temporal-gauge kernel with one right-hand side per thread keeps the
-    // links of all directions live and spills (256 VGPRs); the two-sided
-    // kernel with the second side inactive does not (116 VGPRs).
-    const int k = (L.temporal && sh.rhs_per_thread == 1) ? 2 : sh.rhs_per_thread;
-    switch (k) {
+    switch (sh.rhs_per_thread) {
     case 1: launch_k<P, R, 1>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
     case 2: launch_k<P, R, 2>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;
     case 4: launch_k<P, R, 4>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s); break;

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, LinkRef L, const cha
             for (int j = 0; j < 3; ++j) o[3 * i + j] = make_double2(coeff * pi[j][i].re, -coeff * pi[j][i].im);
         return;
     }
-    const M3<double> u = LinkIO<F64, 18>::load((const char *)L.base + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+    const M3<double> u = LinkIO<F64, 18>::load((const char *)L.base + (2 * mu + parity) * L.block_bytes, L.pitch, cb);
     Cx<double> a[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)

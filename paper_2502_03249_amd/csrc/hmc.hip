@@ -340,7 +340,8 @@ void gauge_repack(Gauge &gauge, const double *U, hipStream_t s)
 {
     for (int prec = 0; prec < 3; ++prec)
         for (int rc = 0; rc < 2; ++rc)
-            if (gauge.fmt[prec][rc]) launch_pack_links(gauge.g, U, prec, rc ? 12 : 18, gauge.fmt[prec][rc], s);
+            if (gauge.fmt[prec][rc])
+                launch_pack_links(gauge.g, U, prec, rc ? 12 : 18, gauge.pitch, gauge.fmt[prec][rc], s);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,12 +358,13 @@ struct WsGauge {
         g.g = geom;
         g.vh = geom.vh;
         g.temporal = false;
+        g.pitch = geom.vh;
         const int rcs[2] = {18, inner_recon};
         const int precs[2] = {F64, inner_prec};
         for (int k = 0; k < 2; ++k) {
             const int rc = rcs[k] == 12 ? 1 : 0;
             if (g.fmt[precs[k]][rc]) continue;
-            const size_t bytes = (size_t)link_block_bytes_per_site(precs[k], rcs[k]) * g.vh * 8;
+            const size_t bytes = (size_t)link_block_bytes_per_site(precs[k], rcs[k]) * g.pitch * 8;
             g.fmt[precs[k]][rc] = ctx.workspace(std::string("hmc.links.") + std::to_string(precs[k]) + "." +
                                                     std::to_string(rcs[k]),
                                                 bytes);

@@ -68,22 +68,21 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
         const bool nb = !((s.negb >> mu) & 1);
         // temporal gauge (Sec. 4.3): the t-links are unit matrices except on
         // the last time slice; they are not read from the link arrays, the
-        // one stored unit link (vh = 1, always cached) is read instead.
-        // Selecting the address keeps the code free of branches (a branch
-        // around the product quadruples the register count of this loop).
+        // unit link stored at index vh of the t-link blocks (always cached)
+        // is read instead.  Selecting the site index keeps the code free of
+        // branches (a branch around the product quadruples the register
+        // count of this loop, a second base address doubles it).
         const bool uf_unit = TG && mu == 3 && (s.tunit & 1u);
         const bool ub_unit = TG && mu == 3 && (s.tunit & 2u);
-        const M3<T> uf = LinkIO<P, R, NT>::load(uf_unit ? (const char *)L.unit : lb + (2 * mu + parity) * L.block_bytes,
-                                                uf_unit ? 1 : g.vh, uf_unit ? 0 : cb);
+        const M3<T> uf = LinkIO<P, R, NT>::load(lb + (2 * mu + parity) * L.block_bytes, L.pitch, uf_unit ? g.vh : cb);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!active[j]) continue;
             const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
             accum(acc[j], mv(uf, v), nf);
         }
-        const M3<T> ub = LinkIO<P, R, NT>::load(ub_unit ? (const char *)L.unit
-                                                        : lb + (2 * mu + 1 - parity) * L.block_bytes,
-                                                ub_unit ? 1 : g.vh, ub_unit ? 0 : s.bwd[mu]);
+        const M3<T> ub = LinkIO<P, R, NT>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, L.pitch,
+                                                ub_unit ? g.vh : s.bwd[mu]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!active[j]) continue;
@@ -104,9 +103,9 @@ __device__ __forceinline__ V3<typename RealOf<P>::type> hop_site_fn(const Geom &
     V3<T> acc = vzero<T>();
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, g.vh, cb);
+        const M3<T> uf = LinkIO<P, R>::load(lb + (2 * mu + parity) * L.block_bytes, L.pitch, cb);
         accum(acc, mv(uf, load(s.fwd[mu])), (s.negf >> mu) & 1);
-        const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, g.vh, s.bwd[mu]);
+        const M3<T> ub = LinkIO<P, R>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, L.pitch, s.bwd[mu]);
         accum(acc, mdv(ub, load(s.bwd[mu])), !((s.negb >> mu) & 1));
     }
     return acc;

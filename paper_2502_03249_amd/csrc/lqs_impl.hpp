@@ -77,10 +77,15 @@ struct CgState {
 
 struct LinkRef {
     const void *base;      // start of the 8 (mu, parity) blocks
-    int64_t block_bytes;   // bytes of one block = bytes_per_site * vh
+    int64_t block_bytes;   // bytes of one block = bytes_per_site * pitch
     int32_t temporal;      // links in temporal gauge: U_t = 1 except leaving t = Nt - 1
-    const void *unit;      // temporal: one unit link in this format's layout with vh = 1
+    int32_t pitch;         // sites per word plane: vh, or vh + TEMPORAL_PAD in temporal gauge,
+                           // where the two t-link blocks hold a unit link at index vh
 };
+
+// Extra sites per word plane of a temporal-gauge link format (keeps the
+// planes 64-site aligned; index vh of the t-link blocks is the unit link).
+constexpr int TEMPORAL_PAD = 64;
 
 struct FieldRef {
     void *data;
@@ -128,15 +133,14 @@ struct Gauge {
     Geom g{};
     int64_t vh = 0;
     void *fmt[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][recon==12]
-    void *unit[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}; // temporal only
     bool temporal = false;
+    int64_t pitch = 0;  // sites per word plane of every format (LinkRef::pitch)
     LinkRef ref(int prec, int recon) const
     {
         const int rc = recon == 12 ? 1 : 0;
         const void *p = fmt[prec][rc];
         LQS_REQUIRE(p != nullptr, LQS_EUNSUPPORTED, "gauge does not hold the requested link format");
-        LQS_REQUIRE(!temporal || unit[prec][rc] != nullptr, LQS_EHIP, "temporal gauge without unit link");
-        return {p, (int64_t)link_block_bytes_per_site(prec, recon) * vh, temporal ? 1 : 0, unit[prec][rc]};
+        return {p, (int64_t)link_block_bytes_per_site(prec, recon) * pitch, temporal ? 1 : 0, (int32_t)pitch};
     }
     ~Gauge();
 };
@@ -148,9 +152,10 @@ int64_t field_bytes(const Geom &g, int prec, int nrhs);
 // launch entry points (one kernel file each)
 
 // pack.hip
-void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, void *out, hipStream_t s);
-// one unit link in the (prec, recon) layout with vh = 1 (at most 64 bytes)
-void launch_unit_link(int prec, int recon, void *out, hipStream_t s);
+void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, int64_t pitch, void *out,
+                       hipStream_t s);
+// the unit link at index vh of the two t-link blocks of a temporal-gauge format
+void launch_unit_link(const Geom &g, int prec, int recon, int64_t pitch, void *links, hipStream_t s);
 void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s);
 void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s);
 void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);

@@ -8,30 +8,36 @@
 namespace lqs {
 
 // ---------------------------------------------------------------------------
-// one unit link in a link format's layout with vh = 1 (the temporal-gauge
-// hop reads it in place of the unit t-links, so that skipping them needs no
-// branch around the product)
+// the unit link stored at index vh (a padding site) of the two t-link blocks
+// of a temporal-gauge format: the hop reads it in place of a unit t-link by
+// changing only the site index, so skipping those links needs no branch
+// around the product and no second base address
 
-template <int P, int R> __global__ void unit_link_kernel(void *out)
+template <int P, int R> __global__ void unit_link_kernel(char *links, int64_t block_bytes, int64_t pitch, int vh)
 {
-    M3<typename RealOf<P>::type> u = m3_unit<typename RealOf<P>::type>();
-    LinkIO<P, R>::store(out, 1, 0, u);
+    const M3<typename RealOf<P>::type> u = m3_unit<typename RealOf<P>::type>();
+    LinkIO<P, R>::store(links + (6 + threadIdx.x) * block_bytes, pitch, vh, u);
 }
 
-void launch_unit_link(int prec, int recon, void *out, hipStream_t s)
+void launch_unit_link(const Geom &g, int prec, int recon, int64_t pitch, void *links, hipStream_t s)
 {
-    if (prec == F64 && recon == 18) hipLaunchKernelGGL((unit_link_kernel<F64, 18>), dim3(1), dim3(1), 0, s, out);
-    else if (prec == F64) hipLaunchKernelGGL((unit_link_kernel<F64, 12>), dim3(1), dim3(1), 0, s, out);
-    else if (prec == F32 && recon == 18) hipLaunchKernelGGL((unit_link_kernel<F32, 18>), dim3(1), dim3(1), 0, s, out);
-    else if (prec == F32) hipLaunchKernelGGL((unit_link_kernel<F32, 12>), dim3(1), dim3(1), 0, s, out);
-    else if (recon == 18) hipLaunchKernelGGL((unit_link_kernel<F16, 18>), dim3(1), dim3(1), 0, s, out);
-    else hipLaunchKernelGGL((unit_link_kernel<F16, 12>), dim3(1), dim3(1), 0, s, out);
+    LQS_REQUIRE(pitch > g.vh, LQS_EINVAL, "temporal-gauge link planes need a padding site");
+    const int64_t bb = (int64_t)link_block_bytes_per_site(prec, recon) * pitch;
+    char *l = (char *)links;
+#define LQS_UNIT(P, R) hipLaunchKernelGGL((unit_link_kernel<P, R>), dim3(1), dim3(2), 0, s, l, bb, pitch, (int)g.vh)
+    if (prec == F64 && recon == 18) LQS_UNIT(F64, 18);
+    else if (prec == F64) LQS_UNIT(F64, 12);
+    else if (prec == F32 && recon == 18) LQS_UNIT(F32, 18);
+    else if (prec == F32) LQS_UNIT(F32, 12);
+    else if (recon == 18) LQS_UNIT(F16, 18);
+    else LQS_UNIT(F16, 12);
+#undef LQS_UNIT
     LQS_HIP(hipGetLastError());
 }
 
 
 template <int P, int R>
-__global__ void pack_links_kernel(Geom g, const double2 *canon, char *out, int64_t block_bytes)
+__global__ void pack_links_kernel(Geom g, const double2 *canon, char *out, int64_t block_bytes, int64_t pitch)
 {
     typedef typename RealOf<P>::type T;
     const int64_t V = 2 * (int64_t)g.vh;
@@ -46,26 +52,29 @@ __global__ void pack_links_kernel(Geom g, const double2 *canon, char *out, int64
         double2 d = src[k];
         u.e[k / 3][k % 3] = {(T)d.x, (T)d.y};
     }
-    LinkIO<P, R>::store(out + (2 * mu + parity) * block_bytes, g.vh, cb, u);
+    LinkIO<P, R>::store(out + (2 * mu + parity) * block_bytes, pitch, cb, u);
 }
 
-template <int P, int R> static void pack_links_t(const Geom &g, const double *canon, void *out, hipStream_t s)
+template <int P, int R>
+static void pack_links_t(const Geom &g, const double *canon, int64_t pitch, void *out, hipStream_t s)
 {
-    const int64_t block_bytes = (int64_t)link_block_bytes_per_site(P, R) * g.vh;
+    const int64_t block_bytes = (int64_t)link_block_bytes_per_site(P, R) * pitch;
     dim3 grid((g.vh + 255) / 256, 8);
     hipLaunchKernelGGL((pack_links_kernel<P, R>), grid, dim3(256), 0, s, g, (const double2 *)canon, (char *)out,
-                       block_bytes);
+                       block_bytes, pitch);
     LQS_HIP(hipGetLastError());
 }
 
-void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, void *out, hipStream_t s)
+void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, int64_t pitch, void *out,
+                       hipStream_t s)
 {
-    if (prec == F64 && recon == 18) pack_links_t<F64, 18>(g, canon, out, s);
-    else if (prec == F64) pack_links_t<F64, 12>(g, canon, out, s);
-    else if (prec == F32 && recon == 18) pack_links_t<F32, 18>(g, canon, out, s);
-    else if (prec == F32) pack_links_t<F32, 12>(g, canon, out, s);
-    else if (recon == 18) pack_links_t<F16, 18>(g, canon, out, s);
-    else pack_links_t<F16, 12>(g, canon, out, s);
+    LQS_REQUIRE(pitch >= g.vh, LQS_EINVAL, "link plane pitch below the site count");
+    if (prec == F64 && recon == 18) pack_links_t<F64, 18>(g, canon, pitch, out, s);
+    else if (prec == F64) pack_links_t<F64, 12>(g, canon, pitch, out, s);
+    else if (prec == F32 && recon == 18) pack_links_t<F32, 18>(g, canon, pitch, out, s);
+    else if (prec == F32) pack_links_t<F32, 12>(g, canon, pitch, out, s);
+    else if (recon == 18) pack_links_t<F16, 18>(g, canon, pitch, out, s);
+    else pack_links_t<F16, 12>(g, canon, pitch, out, s);
 }
 
 // ---------------------------------------------------------------------------

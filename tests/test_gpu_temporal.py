@@ -78,3 +78,23 @@ def test_solve_in_temporal_gauge_maps_back(ctx):
     # U' equals G U G^dag to ~1e-16 per entry, so ||b - M x|| / ||b|| differs from the
     # fixed-gauge residual by at most ~1e-16 * ||M|| ||x|| / ||b|| <= 1e-16 * 64 / m^2 = 2.6e-12
     assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10 + 3e-12
+
+
+@pytest.mark.parametrize("prec,recon,nrhs,bound", [(lqs.F64, 18, 3, 1e-12), (lqs.F32, 12, 5, 2e-6),
+                                                   (lqs.F16, 12, 2, 4e-3), (lqs.F64, 12, 1, 1e-12)])
+def test_temporal_hop_multi_rhs_and_dagger(ctx, prec, recon, nrhs, bound):
+    """Several right-hand sides per link read (one, two and four per thread, groups with an
+    inactive side) and the dagger, on a lattice whose 96-site time slices split wavefronts,
+    so that unit and stored t-links meet inside one wavefront."""
+    dims = (4, 6, 8, 10)
+    U = synth.gauge(dims, "haar", seed=117)
+    Uf = host(lqs.gauge_fix_temporal(ctx, dims, dev(U))[0])
+    g = lqs.Gauge(ctx, dims, dev(Uf), lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+    srcs = np.stack([synth.source(dims, 1, seed=1170 + k) for k in range(nrhs)])
+    x = field(ctx, dims, srcs, 1, prec)
+    got = lex_of(ctx, lqs.dslash_apply(ctx, g, x, recon=recon), squeeze=False)
+    gotd = lex_of(ctx, lqs.dslash_dagger(ctx, g, x, recon=recon), squeeze=False)
+    for k in range(nrhs):
+        want = oracle.dslash(dims, Uf, srcs[k], 0)
+        assert rel(got[k], want) <= bound
+        assert rel(gotd[k], oracle.dslash_dagger(dims, Uf, srcs[k], 0)) <= bound
