@@ -61,11 +61,18 @@ __device__ void fin_update(CgState &S, double r2)
     if (S.rel_interval > 0 && (S.since_rel >= S.rel_interval || r2 < S.delta2 * S.max_rho)) S.reliable_pending = 1;
 }
 
-// mode: 0 reliable update inside the iteration, 1 initial residual, 2 measure only
+// mode: 0 reliable update inside the iteration, 1 initial residual, 2 measure
+// only, 3 periodic update with the reconstructed FP64 links (a residual that
+// meets the target is handed on, still pending, to the mode-0 check with the
+// stored links instead of ending the solve)
 __device__ void fin_residual(CgState &S, double r2, int mode)
 {
     S.true_r2 = r2;
     if (mode == 2) return;
+    if (mode == 3 && isfinite(r2) && r2 <= S.stop2) {
+        S.phase = CG_INNER_DONE;
+        return;
+    }
     if (mode == 1) {
         S.rho = r2;
         S.max_rho = r2;
@@ -269,8 +276,8 @@ __global__ void __launch_bounds__(BLAS_BLOCK) accumulate_kernel(int vh, double *
 }
 
 // r_hi = b - (m^2 x - D_eo t64) in FP64, |r_hi|^2; r (PA) = r_hi unless mode 2.
-// gate_mode 2: only right-hand sides with a pending update; 0: all.
-template <int R, int PA, int K>
+// gate_mode as in gate_state (0: all right-hand sides).
+template <int R, int PA, int K, int LF>
 __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const char *t64, const char *x,
                                                        const char *b, char *r, int64_t sa, double m2, CgState *st,
                                                        double *partials, int max_blocks, int nrhs, int gate_mode,
@@ -284,7 +291,7 @@ __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const 
     bool any = false;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        blk[j] = (r0 + j < nrhs) && (gate_mode == 0 || st[r0 + j].reliable_pending);
+        blk[j] = (r0 + j < nrhs) && gate_state(st[r0 + j], gate_mode);
         act[j] = blk[j] && valid;
         any |= blk[j];
     }
@@ -293,7 +300,7 @@ __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const 
     double nrm[K];
     if (valid) {
         const Site s = decode(g, cb, 0);
-        hop_site<F64, R, K>(g, L, 0, s, cb, t64 + r0 * s64, s64, act, acc);
+        hop_site<F64, R, K, LF>(g, L, 0, s, cb, t64 + r0 * s64, s64, act, acc);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -363,7 +370,7 @@ __global__ void __launch_bounds__(1024) finalize_kernel(CgState *st, const doubl
     CgState &S = st[r];
     bool active = true;
     if (mode == FIN_DOT || mode == FIN_UPDATE) active = S.phase == CG_RUNNING;
-    else if (mode == FIN_RESID) active = gate_mode == 0 || S.reliable_pending;
+    else if (mode == FIN_RESID) active = gate_state(S, gate_mode);
     if (!active) return;
     const double *p = partials + (int64_t)r * max_blocks;
     double acc = 0.0;
@@ -471,33 +478,48 @@ static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, int n
     if (which == 0) launch_finalize(v, v.partials2, grid.x, FIN_UPDATE, 0, 0, s);
 }
 
-template <int PA>
-static void launch_residual_t(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+template <int PA, int R, int K>
+static void launch_residual_k(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
 {
     const Geom &g = gauge.g;
     const int block = 256;
-    const int K = v.nrhs >= 2 ? 2 : 1;
-    dim3 grid((g.vh + block - 1) / block, (v.nrhs + K - 1) / K);
-    const LinkRef L = gauge.ref(F64, 18);
+    const dim3 grid((g.vh + block - 1) / block, (v.nrhs + K - 1) / K);
+    const LinkRef L = gauge.ref(F64, R);
+    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (default_hop_shape(L, v.nrhs).stream_links ? LF_STREAM : 0);
     const int64_t sa = field_bytes(g, PA, 1);
     char *r = (char *)(mode == 2 ? nullptr : v.r);
     const double m2 = v.mass * v.mass;
-    if (K == 1)
-        hipLaunchKernelGGL((residual_kernel<18, PA, 1>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,
-                           (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
-                           gate_mode, mode);
-    else
-        hipLaunchKernelGGL((residual_kernel<18, PA, 2>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,
-                           (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,
-                           gate_mode, mode);
+#define LQS_RES(LF)                                                                                               \
+    hipLaunchKernelGGL((residual_kernel<R, PA, K, LF>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,       \
+                       (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,  \
+                       gate_mode, mode)
+    switch (lf) {
+    case 0: LQS_RES(0); break;
+    case LF_TEMPORAL: LQS_RES(LF_TEMPORAL); break;
+    case LF_STREAM: LQS_RES(LF_STREAM); break;
+    default: LQS_RES(LF_TEMPORAL | LF_STREAM); break;
+    }
+#undef LQS_RES
     LQS_HIP(hipGetLastError());
     launch_finalize(v, v.partials, grid.x, FIN_RESID, gate_mode, mode, s);
 }
 
-static void launch_residual(const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
+// FP64 residual with the R-real FP64 links (two right-hand sides per thread
+// from two on)
+static void launch_residual(const Gauge &gauge, const CgVectors &v, int R, int gate_mode, int mode, hipStream_t s)
 {
-    if (v.acc_prec == F64) launch_residual_t<F64>(gauge, v, gate_mode, mode, s);
-    else launch_residual_t<F32>(gauge, v, gate_mode, mode, s);
+    const bool two = v.nrhs >= 2;
+#define LQS_RES_PA(PA)                                                                                            \
+    if (R == 12 && two) launch_residual_k<PA, 12, 2>(gauge, v, gate_mode, mode, s);                               \
+    else if (R == 12) launch_residual_k<PA, 12, 1>(gauge, v, gate_mode, mode, s);                                 \
+    else if (two) launch_residual_k<PA, 18, 2>(gauge, v, gate_mode, mode, s);                                     \
+    else launch_residual_k<PA, 18, 1>(gauge, v, gate_mode, mode, s)
+    if (v.acc_prec == F64) {
+        LQS_RES_PA(F64);
+    } else {
+        LQS_RES_PA(F32);
+    }
+#undef LQS_RES_PA
 }
 
 static void launch_accumulate(const Gauge &gauge, const CgVectors &v, int gated, hipStream_t s)
@@ -511,15 +533,31 @@ static void launch_accumulate(const Gauge &gauge, const CgVectors &v, int gated,
     LQS_HIP(hipGetLastError());
 }
 
+// t64 = D_oe x and the residual kernel with the R-real FP64 links
+static void residual_pass(const Gauge &gauge, const CgVectors &v, int R, int gate_mode, int mode, hipStream_t s)
+{
+    const LinkRef L64 = gauge.ref(F64, R);
+    const LaunchShape sh = default_hop_shape(L64, v.nrhs);
+    launch_hop_gated(gauge.g, L64, F64, R, 0, 1, v.nrhs, v.x, v.t64, v.state, gate_mode, sh, s);
+    launch_residual(gauge, v, R, gate_mode, mode, s);
+}
+
 // The FP64 residual group: x += x_lo (mixed), t64 = D_oe x, residual kernel.
+// In a mixed solve on 12-real links the periodic reliable updates use the
+// FP64 12-real links (two thirds of the bytes); the update that decides
+// convergence always uses the stored 18-real links, so the reported residual
+// is that of the operator the caller passed.
 void cg_residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s)
 {
     (void)ctx;
-    if (v.acc_prec != F64 && mode == 0) launch_accumulate(gauge, v, gate_mode == 2 ? 1 : 0, s);
-    const LinkRef L64 = gauge.ref(F64, 18);
-    const LaunchShape sh = default_hop_shape(L64, v.nrhs);
-    launch_hop_gated(gauge.g, L64, F64, 18, 0, 1, v.nrhs, v.x, v.t64, v.state, gate_mode, sh, s);
-    launch_residual(gauge, v, gate_mode, mode, s);
+    const bool mixed = v.acc_prec != F64;
+    if (mixed && mode == 0) launch_accumulate(gauge, v, gate_mode == 2 ? 1 : 0, s);
+    if (mixed && mode == 0 && gate_mode == 2 && v.recon == 12 && gauge.fmt[F64][1]) {
+        residual_pass(gauge, v, 12, 3, 3, s);
+        residual_pass(gauge, v, 18, 4, 0, s);
+    } else {
+        residual_pass(gauge, v, 18, gate_mode, mode, s);
+    }
 }
 
 void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_t s)

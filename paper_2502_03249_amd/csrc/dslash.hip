@@ -11,14 +11,6 @@
 
 namespace lqs {
 
-// gate_mode 0: always run; 1: only right-hand sides whose CG phase is
-// RUNNING; 2: only those with a pending FP64 residual update.
-__device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, int r)
-{
-    if (gate_mode == 0) return true;
-    if (gate_mode == 1) return gate[r].phase == CG_RUNNING;
-    return gate[r].reliable_pending != 0;
-}
 
 template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,

@@ -52,6 +52,25 @@ inline int slab_tiles_per_xcd(const Geom &g, int block, int xcd_slab)
     return slab ? (tiles + 7) / 8 : 0;
 }
 
+// Gates of the CG kernels on the state of one right-hand side.  0: always;
+// 1: while RUNNING; 2: an FP64 residual update is pending; 3: pending while
+// RUNNING (a periodic reliable update); 4: pending after the iterated
+// residual met the target (the update that decides convergence).
+__device__ __forceinline__ bool gate_state(const CgState &S, int gate_mode)
+{
+    switch (gate_mode) {
+    case 0: return true;
+    case 1: return S.phase == CG_RUNNING;
+    case 2: return S.reliable_pending != 0;
+    case 3: return S.reliable_pending != 0 && S.phase == CG_RUNNING;
+    default: return S.reliable_pending != 0 && S.phase != CG_RUNNING;
+    }
+}
+__device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, int r)
+{
+    return gate_mode == 0 || gate_state(gate[r], gate_mode);
+}
+
 template <int P, int R, int K, int LF = 0>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
                                          const char *in, int64_t in_stride, const bool *active,
