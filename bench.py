@@ -200,6 +200,7 @@ def main():
     lqs.profile_hops(ctx, False)
     working = sum(s["iters"] for s in stats)
     mixed_s = elapsed / a.steps
+    x_mixed = xf.to_lex(ctx)  # solution of the last timed solve, compared below with the FP64 one
     ok = all(s["status"] == 0 and s["true_rel_residual"] <= TOL for s in stats)
 
     # FP64 solve on the same system (untimed by the step loop, timed on its own)
@@ -209,9 +210,19 @@ def main():
     fp64 = [solve(lqs.F64, 18, 0) for _ in range(2)]
     fp64_s = min(t for t, _ in fp64)
     fp64_st = fp64[0][1]
+    x_fp64 = xf.to_lex(ctx)
     fp64_12 = [solve(lqs.F64, 12, 0) for _ in range(2)]
     fp64_12_s = min(t for t, _ in fp64_12)
     other_t, other_st = solve(other, a.recon, a.reliable)
+    x_other = xf.to_lex(ctx)
+
+    def rel_err(x):
+        # ||x - x_FP64|| / ||x_FP64||: the solve's error against the FP64 solution of the same
+        # system (the FP64 solver itself is checked against the oracle by the test suite)
+        return float(torch.linalg.vector_norm(x - x_fp64) / torch.linalg.vector_norm(x_fp64))
+
+    err_mixed, err_other = rel_err(x_mixed), rel_err(x_other)
+    del x_mixed, x_other
 
     # The paper's storage (Sec. 4.3): the same system in temporal gauge, U' = G U G^dag with
     # U'_t = 1 off the last slice, b' = G b; the hop then reads 6 + 2/Nt links per site.
@@ -224,7 +235,6 @@ def main():
         gt = lqs.Gauge(ctx, dims, Uf, lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
         del Uf
         bt = (G * torch.from_numpy(b).to(dev).unsqueeze(-2)).sum(-1)
-        del G
         btf = lqs.Field.from_lex(ctx, bt, 0)
         del bt
         xtf = btf.like()
@@ -240,10 +250,14 @@ def main():
 
         solve_t(inner, 12, a.reliable)
         tm = [solve_t(inner, 12, a.reliable) for _ in range(2)]
+        # x = G^dag x' maps the fixed-gauge solution back
+        xt = (G.conj().transpose(-1, -2) * xtf.to_lex(ctx)[0].unsqueeze(-2)).sum(-1)
+        err_t = rel_err(xt.unsqueeze(0))
+        del xt, G
         solve_t(lqs.F64, 12, 0)
         t64 = solve_t(lqs.F64, 12, 0)
         temporal = {"mixed_s": round(min(t for t, _ in tm), 5), "mixed_iters": tm[0][1]["iters"],
-                    "mixed_true_res": tm[0][1]["true_rel_residual"],
+                    "mixed_true_res": tm[0][1]["true_rel_residual"], "mixed_x_rel_err_vs_fp64": err_t,
                     "fp64_recon12_s": round(t64[0], 5), "fp64_iters": t64[1]["iters"],
                     "fp64_true_res": t64[1]["true_rel_residual"],
                     "converged": all(st["status"] == 0 and st["true_rel_residual"] <= TOL
@@ -298,13 +312,15 @@ def main():
         "cpu_baseline": cpu,
         "cg": {"mixed_s": round(mixed_s, 5), "mixed_iters": stats[-1]["iters"],
                "mixed_reliable_updates": stats[-1]["reliable_updates"],
-               "mixed_true_res": stats[-1]["true_rel_residual"], "all_converged": ok,
+               "mixed_true_res": stats[-1]["true_rel_residual"], "mixed_x_rel_err_vs_fp64": err_mixed,
+               "all_converged": ok,
                "fp64_s": round(fp64_s, 5), "fp64_iters": fp64_st["iters"], "fp64_true_res": fp64_st["true_rel_residual"],
                "fp64_recon12_s": round(fp64_12_s, 5),
                "speedup_mixed_vs_fp64": round(fp64_s / mixed_s, 3),
                "speedup_mixed_vs_best_fp64": round(min(fp64_s, fp64_12_s) / mixed_s, 3),
                f"{'f32' if other == lqs.F32 else 'f16'}_mixed_s": round(other_t, 5),
                f"{'f32' if other == lqs.F32 else 'f16'}_mixed_iters": other_st["iters"],
+               f"{'f32' if other == lqs.F32 else 'f16'}_mixed_x_rel_err_vs_fp64": err_other,
                "temporal_gauge": temporal},
         "dslash": {"fp64_18_model_GBps": round(h64["model_GBps"], 1), "fp64_18_GFLOPs": round(h64["GFLOPs"], 1),
                    "fp64_18_frac_hbm": round(h64["frac_hbm"], 4),
