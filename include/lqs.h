@@ -189,7 +189,10 @@ typedef struct {
     double tol;                /* stop when ||b - M x|| / ||b|| <= tol (FP64 residual)     */
     int32_t max_iter;          /* cap on iterations per right-hand side                    */
     int32_t inner_prec;        /* LQS_F64: plain FP64 CG; LQS_F32/LQS_F16: mixed precision */
-    int32_t inner_recon;       /* 18 or 12: link format of the inner operator              */
+    int32_t inner_recon;       /* 18 or 12: link format of the inner operator; with 12 and a
+                                  gauge holding FP64 12-real links, the periodic FP64 updates
+                                  of a mixed solve use those, the convergence check always
+                                  the stored 18-real links                                   */
     int32_t reliable_interval; /* mixed: FP64 residual update every K iterations (0: 100)   */
     double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r|| (0: 0.05)     */
     int32_t use_x0;            /* 1: start from x                                           */
