@@ -482,6 +482,17 @@ def run_suite(a):
               "separate_fp64_s": round(t_sep, 4), "speedup": round(t_sep / t_ms, 2),
               "iters": [r["iters"] for r in st[-1]], "true_res": [r["true_rel_residual"] for r in st[-1]],
               "all_converged": all(r["status"] == 0 for r in st[-1])})
+        # the recurrence in FP32 / FP16 storage (12-real links), every mass refined to the FP64 residual
+        for inner in ("f32", "f16"):
+            stm = []
+            lqs.cg_solve_multishift(ctx, g, masses, b, xs, tol=TOL, inner_prec=inner, inner_recon=12)
+            t_mix = timed(lambda: stm.append(lqs.cg_solve_multishift(ctx, g, masses, b, xs, tol=TOL,
+                                                                     inner_prec=inner, inner_recon=12)), 2)
+            emit({"suite": "multishift_mixed", "dims": dims, "masses": masses, "inner": inner, "recon": 12,
+                  "multishift_s": round(t_mix, 4), "fp64_multishift_s": round(t_ms, 4),
+                  "speedup_vs_fp64_multishift": round(t_ms / t_mix, 2),
+                  "iters": [r["iters"] for r in stm[-1]], "true_res": [r["true_rel_residual"] for r in stm[-1]],
+                  "all_converged": all(r["status"] == 0 for r in stm[-1])})
         g.close()
 
     # 3. 16-RHS block CG on 32^3x8 (m 0.02) vs 16 single solves, FP32 inner + FP64 reliable updates

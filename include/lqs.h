@@ -222,14 +222,18 @@ lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const
 
 /* Several masses on one Krylov space: x_i = (m_i^2 - D_eo D_oe)^-1 b for
  * i < nmass (multi-shift CG; the systems differ by the shifts m_i^2 - m_0^2
- * of the smallest mass m_0).  FP64 only: params->inner_prec must be LQS_F64
- * and params->persistent 0; use_x0 is ignored (x_i start from zero).  b is an
- * FP64 native even field (nrhs 1); x is a host array of nmass device pointers
- * to FP64 native even fields, overwritten.  Every x_i is finally checked
- * against its own FP64 true residual and refined by a warm-started CG when
- * the shared recurrence ended above tol.  stats: nmass entries; iters counts
- * the shared iterations while system i was active plus refinement iterations.
- * nmass in 1..17, masses finite and >= 0. */
+ * of the smallest mass m_0).  The shared recurrence keeps its search
+ * directions and applies the operator in params->inner_prec (LQS_F64, LQS_F32
+ * or LQS_F16 storage, links inner_recon; the residual is FP32 unless FP64) and
+ * accumulates every x_i in FP64.  params->persistent must be 0 (else
+ * LQS_EUNSUPPORTED); use_x0 is ignored (x_i start from zero).  b is an FP64
+ * native even field (nrhs 1); x is a host array of nmass device pointers to
+ * FP64 native even fields, overwritten.  Every x_i is finally checked against
+ * its own FP64 true residual and refined, when the shared recurrence ended
+ * above tol, by a warm-started CG with the same params (mixed precision with
+ * reliable updates unless inner_prec is LQS_F64).  stats: nmass entries; iters
+ * counts the shared iterations while system i was active plus refinement
+ * iterations.  nmass in 1..17, masses finite and >= 0. */
 lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, const double *masses, const double *b,
                                double *const *x, const lqs_cg_params *params, lqs_cg_stats *stats, void *stream);
 

@@ -332,15 +332,18 @@ def cg_solve(ctx, problems, tol=1e-10, max_iter=10000, inner_prec=F64, inner_rec
     return [s.as_dict() for s in stats]
 
 
-def cg_solve_multishift(ctx, gauge, masses, b, xs, tol=1e-10, max_iter=10000, inner_recon=18, stream=None):
-    """x_i = (m_i^2 - D_eo D_oe)^-1 b for every mass on one Krylov space (FP64); returns per-mass stats."""
+def cg_solve_multishift(ctx, gauge, masses, b, xs, tol=1e-10, max_iter=10000, inner_prec=F64, inner_recon=18,
+                        reliable_interval=0, reliable_delta=0.0, stream=None):
+    """x_i = (m_i^2 - D_eo D_oe)^-1 b for every mass on one Krylov space (recurrence in inner_prec, solutions
+    in FP64, per-mass FP64 check and refinement); returns per-mass stats."""
     n = len(masses)
     assert len(xs) == n and b.prec == F64 and b.parity == 0 and b.nrhs == 1
     for x in xs:
         assert x.prec == F64 and x.parity == 0 and x.nrhs == 1
     m = (ctypes.c_double * n)(*[float(v) for v in masses])
     ptrs = (ctypes.c_void_p * n)(*[x.data.data_ptr() for x in xs])
-    prm = LqsCgParams(float(tol), int(max_iter), F64, int(inner_recon), 0, 0.0, 0, 0)
+    prm = LqsCgParams(float(tol), int(max_iter), PREC[inner_prec], int(inner_recon), int(reliable_interval),
+                      float(reliable_delta), 0, 0)
     stats = (LqsCgStats * n)()
     st = lib().cg_solve_multishift(ctx.handle, gauge.handle, n, m, ctypes.c_void_p(b.data.data_ptr()), ptrs,
                                    ctypes.byref(prm), stats, _stream(stream))

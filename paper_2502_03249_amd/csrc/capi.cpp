@@ -414,14 +414,16 @@ lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, 
         LQS_REQUIRE(p.tol > 0 && std::isfinite(p.tol), LQS_EINVAL, "tol must be positive");
         LQS_REQUIRE(p.max_iter >= 1, LQS_EINVAL, "max_iter must be >= 1");
         LQS_REQUIRE(p.inner_recon == 18 || p.inner_recon == 12, LQS_EINVAL, "inner_recon must be 18 or 12");
-        LQS_REQUIRE(p.inner_prec == LQS_F64 && !p.persistent, LQS_EUNSUPPORTED, "multi-shift CG runs in FP64");
+        LQS_REQUIRE(p.inner_prec == LQS_F64 || p.inner_prec == LQS_F32 || p.inner_prec == LQS_F16, LQS_EINVAL,
+                    "inner_prec must be LQS_F64, LQS_F32 or LQS_F16");
+        LQS_REQUIRE(!p.persistent, LQS_EUNSUPPORTED, "multi-shift CG has no persistent form");
         check_ptr(b, "b");
         for (int i = 0; i < nmass; ++i) {
             LQS_REQUIRE(std::isfinite(masses[i]) && masses[i] >= 0, LQS_EINVAL, "masses must be finite and >= 0");
             check_ptr(x[i], "x[i]");
             for (int j = 0; j < i; ++j) LQS_REQUIRE(x[i] != x[j], LQS_EINVAL, "solution fields must be distinct");
         }
-        (void)g->ref(LQS_F64, p.inner_recon);
+        (void)g->ref(p.inner_prec, p.inner_recon);
         LQS_HIP(hipSetDevice(ctx->device));
         multishift_solve(*ctx, *g, nmass, masses, b, x, p, stats, as_stream(stream));
         for (int i = 0; i < nmass; ++i) {

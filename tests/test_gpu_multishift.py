@@ -41,7 +41,8 @@ def test_multishift_matches_separate_solves(ctx, dims, kind, masses):
     assert iters[0] == base_iters
 
 
-def test_multishift_rejects_mixed_precision(ctx):
+def test_multishift_argument_errors(ctx):
+    """No persistent form (LQS_EUNSUPPORTED); an unknown precision or aliased solutions are LQS_EINVAL."""
     dims = (4, 4, 4, 4)
     g = gauge(ctx, dims, synth.gauge(dims, "haar", seed=1))
     bf = field(ctx, dims, synth.source(dims, 0, seed=2), 0)
@@ -49,13 +50,32 @@ def test_multishift_rejects_mixed_precision(ctx):
     import ctypes
     m = (ctypes.c_double * 2)(0.1, 0.2)
     ptrs = (ctypes.c_void_p * 2)(*[x.data.data_ptr() for x in xs])
-    prm = lqs.LqsCgParams(1e-10, 100, lqs.F32, 18, 0, 0.0, 0, 0)
     stats = (lqs.LqsCgStats * 2)()
-    st = lqs.lib().cg_solve_multishift(ctx.handle, g.handle, 2, m, ctypes.c_void_p(bf.data.data_ptr()), ptrs,
-                                       ctypes.byref(prm), stats, None)
-    assert st == lqs.EUNSUPPORTED
+
+    def call(prm, p=ptrs):
+        return lqs.lib().cg_solve_multishift(ctx.handle, g.handle, 2, m, ctypes.c_void_p(bf.data.data_ptr()), p,
+                                             ctypes.byref(prm), stats, None)
+
+    assert call(lqs.LqsCgParams(1e-10, 100, lqs.F32, 18, 0, 0.0, 0, 1)) == lqs.EUNSUPPORTED
+    assert call(lqs.LqsCgParams(1e-10, 100, 3, 18, 0, 0.0, 0, 0)) == lqs.EINVAL
     ptrs2 = (ctypes.c_void_p * 2)(xs[0].data.data_ptr(), xs[0].data.data_ptr())
-    prm.inner_prec = lqs.F64
-    st = lqs.lib().cg_solve_multishift(ctx.handle, g.handle, 2, m, ctypes.c_void_p(bf.data.data_ptr()), ptrs2,
-                                       ctypes.byref(prm), stats, None)
-    assert st == lqs.EINVAL
+    assert call(lqs.LqsCgParams(1e-10, 100, lqs.F64, 18, 0, 0.0, 0, 0), ptrs2) == lqs.EINVAL
+
+
+@pytest.mark.parametrize("prec,recon", [(lqs.F32, 12), (lqs.F16, 12), (lqs.F32, 18)])
+def test_multishift_mixed_precision(ctx, prec, recon):
+    """Recurrence with FP32 / FP16-storage search directions and operator, solutions accumulated
+    in FP64, then per-mass FP64 checks with mixed-precision refinement: every mass reaches the
+    FP64 true residual against the oracle."""
+    dims, masses = (16, 16, 16, 8), [0.02, 0.05, 0.1, 0.4, 1.5]
+    U = synth.gauge(dims, "smooth", seed=103, eps=0.3)
+    b = synth.source(dims, 0, seed=104)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xs = [bf.like() for _ in masses]
+    st = lqs.cg_solve_multishift(ctx, g, masses, bf, xs, tol=1e-10, inner_prec=prec, inner_recon=recon)
+    for m, x, s in zip(masses, xs, st):
+        assert s["status"] == 0, s
+        xv = lex_of(ctx, x)
+        assert oracle.true_residual(dims, U, m, b, xv) <= 1e-10
+        assert abs(oracle.true_residual(dims, U, m, b, xv) - s["true_rel_residual"]) <= 1e-12
