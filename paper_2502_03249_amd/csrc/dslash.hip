@@ -20,8 +20,9 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
     typedef typename RealOf<P>::type T;
     int tile, grp;
     tile_group(ngroups, tpx, tile, grp);
-    const int cb = tile * blockDim.x + threadIdx.x;
-    if (cb >= g.vh) return;
+    const int c0 = tile * blockDim.x;
+    if (c0 >= g.vh) return;  // padding tile (whole block)
+    const int cb = c0 + threadIdx.x;
     const int r0 = grp * K;
     bool active[K];
     bool any = false;
@@ -30,10 +31,26 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
         active[j] = (r0 + j < nrhs) && gate_open(gate, gate_mode, r0 + j);
         any |= active[j];
     }
-    if (!any) return;
+    if (!any) return;  // uniform over the block
+    extern __shared__ __align__(16) char win[];
+    int w0 = 0, wlen = 0;
+    const int wstride = (int)(spinor_bytes_per_site(P) * (blockDim.x + g.n[0] + 2));
+    if (LF & LF_LDS) {
+        // x and y neighbours of [c0, c0 + B) lie in [c0 - Nx/2 - 1, c0 + B + Nx/2 + 1)
+        // except across periodic boundaries, which are read from memory
+        const int h = g.n[0] / 2 + 1;
+        w0 = c0 - h > 0 ? c0 - h : 0;
+        const int w1 = c0 + (int)blockDim.x + h < g.vh ? c0 + (int)blockDim.x + h : g.vh;
+        wlen = w1 - w0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (active[j]) stage_window<P>(in + (r0 + j) * in_stride, g.vh, win + j * wstride, w0, wlen);
+        __syncthreads();
+    }
+    if (cb >= g.vh) return;
     const Site s = decode(g, cb, parity);
     V3<T> acc[K];
-    hop_site<P, R, K, LF>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc);
+    hop_site<P, R, K, LF>(g, L, parity, s, cb, in + r0 * in_stride, in_stride, active, acc, win, wstride, w0, wlen);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!active[j]) continue;
@@ -54,9 +71,10 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
     const int tiles = (g.vh + sh.block - 1) / sh.block, G = (nrhs + K - 1) / K;
     const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
     const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
-    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
+    const size_t lds = hop_lds_bytes(g, P, K, sh, L.temporal != 0);
+    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
 #define LQS_HOP(DAG, LF)                                                                                         \
-    hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), 0, s, g, L, parity, nrhs,            \
+    hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), lds, s, g, L, parity, nrhs,          \
                        (const char *)in, stride, (char *)out, stride, gate, gate_mode, G, tpx)
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
@@ -65,7 +83,10 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
     case 0: LQS_HOP_LF(0); break;
     case LF_TEMPORAL: LQS_HOP_LF(LF_TEMPORAL); break;
     case LF_STREAM: LQS_HOP_LF(LF_STREAM); break;
-    default: LQS_HOP_LF(LF_TEMPORAL | LF_STREAM); break;
+    case LF_TEMPORAL | LF_STREAM: LQS_HOP_LF(LF_TEMPORAL | LF_STREAM); break;
+    case LF_LDS: LQS_HOP_LF(LF_LDS); break;
+    case LF_LDS | LF_STREAM: LQS_HOP_LF(LF_LDS | LF_STREAM); break;
+    default: throw Error(LQS_EINVAL, "unexpected link flags");
     }
 #undef LQS_HOP_LF
 #undef LQS_HOP

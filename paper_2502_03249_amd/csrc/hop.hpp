@@ -16,7 +16,7 @@ namespace lqs {
 // sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
 // the input field (parity 1 - parity); consecutive sides are in_stride bytes
 // apart.
-enum { LF_TEMPORAL = 1, LF_STREAM = 2 };
+enum { LF_TEMPORAL = 1, LF_STREAM = 2, LF_LDS = 4 };
 
 // Block -> (site tile, right-hand-side group).  Consecutive block indices go
 // to the 8 XCDs in turn, each with its own L2; two maps build on that:
@@ -71,10 +71,45 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
     return gate_mode == 0 || gate_state(gate[r], gate_mode);
 }
 
+// LDS bytes of the staged input window of a hop launch: K sides of B + Nx + 2
+// sites; 0 (no staging) unless the shape asks for it, the links are not in
+// temporal gauge (that variant is not built) and the window fits in 64 KiB.
+inline size_t hop_lds_bytes(const Geom &g, int prec, int K, const LaunchShape &sh, bool temporal = false)
+{
+    if (!sh.lds || temporal) return 0;
+    const size_t b = (size_t)K * spinor_bytes_per_site(prec) * (sh.block + g.n[0] + 2);
+    return b <= 65536 ? b : 0;
+}
+
+// Copy sites [w0, w0 + wlen) of one colour-vector field into an LDS window
+// laid out like the field with wlen sites per plane.
+template <int P> __device__ __forceinline__ void stage_window(const char *src, int64_t vh, char *dst, int w0, int wlen);
+template <> __device__ __forceinline__ void stage_window<F64>(const char *src, int64_t vh, char *dst, int w0, int wlen)
+{
+    for (int k = 0; k < 3; ++k)
+        for (int i = threadIdx.x; i < wlen; i += blockDim.x)
+            ((double2 *)dst)[k * wlen + i] = ((const double2 *)src)[k * vh + w0 + i];
+}
+template <> __device__ __forceinline__ void stage_window<F32>(const char *src, int64_t vh, char *dst, int w0, int wlen)
+{
+    for (int i = threadIdx.x; i < wlen; i += blockDim.x) {
+        ((float4 *)dst)[i] = ((const float4 *)src)[w0 + i];
+        ((float2 *)((float4 *)dst + wlen))[i] = ((const float2 *)((const float4 *)src + vh))[w0 + i];
+    }
+}
+template <> __device__ __forceinline__ void stage_window<F16>(const char *src, int64_t vh, char *dst, int w0, int wlen)
+{
+    (void)vh;
+    for (int i = threadIdx.x; i < wlen; i += blockDim.x) ((uint4 *)dst)[i] = ((const uint4 *)src)[w0 + i];
+}
+
+// LF_LDS: the x and y neighbours of a block's sites come from an LDS window
+// (win: right-hand side 0; win_stride bytes per side; sites [w0, w0 + wlen)).
 template <int P, int R, int K, int LF = 0>
 __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int parity, const Site &s, int cb,
                                          const char *in, int64_t in_stride, const bool *active,
-                                         V3<typename RealOf<P>::type> *acc)
+                                         V3<typename RealOf<P>::type> *acc, const char *win = nullptr,
+                                         int win_stride = 0, int w0 = 0, int wlen = 0)
 {
     typedef typename RealOf<P>::type T;
     constexpr bool TG = (LF & LF_TEMPORAL) != 0, NT = (LF & LF_STREAM) != 0;
@@ -97,7 +132,10 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!active[j]) continue;
-            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.fwd[mu]);
+            const int nbr = s.fwd[mu];
+            const bool lw = (LF & LF_LDS) && mu < 2 && nbr >= w0 && nbr < w0 + wlen;
+            const V3<T> v = lw ? SpinorIO<P>::load(win + j * win_stride, wlen, nbr - w0)
+                               : SpinorIO<P>::load(in + j * in_stride, g.vh, nbr);
             accum(acc[j], mv(uf, v), nf);
         }
         const M3<T> ub = LinkIO<P, R, NT>::load(lb + (2 * mu + 1 - parity) * L.block_bytes, L.pitch,
@@ -105,7 +143,10 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!active[j]) continue;
-            const V3<T> v = SpinorIO<P>::load(in + j * in_stride, g.vh, s.bwd[mu]);
+            const int nbr = s.bwd[mu];
+            const bool lw = (LF & LF_LDS) && mu < 2 && nbr >= w0 && nbr < w0 + wlen;
+            const V3<T> v = lw ? SpinorIO<P>::load(win + j * win_stride, wlen, nbr - w0)
+                               : SpinorIO<P>::load(in + j * in_stride, g.vh, nbr);
             accum(acc[j], mdv(ub, v), nb);
         }
     }

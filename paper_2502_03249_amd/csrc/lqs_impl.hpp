@@ -170,6 +170,7 @@ struct LaunchShape {
     int rhs_per_thread = 1;
     int stream_links = 0;  // 1: link words fetched with streaming (nontemporal) loads
     int xcd_slab = -1;     // block -> tile map: 0 round robin, 1 one slab per XCD, -1 by lattice shape
+    int lds = 0;           // 1: x and y neighbours from an LDS window of the block's input sites
 };
 // Link footprint from which the hop streams its links by default: beyond
 // about three quarters of the 256 MB last-level cache (MALL) the links of one
@@ -240,7 +241,7 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
 // tune.cpp
 struct Tuner {
     std::string path;
-    std::map<std::string, std::string> cache;  // key -> "block,rhs_per_thread,stream_links,xcd_slab"
+    std::map<std::string, std::string> cache;  // key -> "block,rhs_per_thread,stream_links,xcd_slab,lds"
     explicit Tuner(const char *p);
     bool lookup(const std::string &key, LaunchShape &out, int max_block = 512) const;
     void store(const std::string &key, const LaunchShape &v);

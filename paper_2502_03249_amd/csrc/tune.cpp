@@ -3,10 +3,11 @@
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
 // thread x cached or streaming link loads, then the other block -> XCD map
-// for the best of these) with HIP events on the caller's stream, keeps the
-// one with the lowest median time, and stores it in a flat JSON object
-// {"key": "block,rhs_per_thread,stream_links,xcd_slab", ...} that later runs
-// load.  Tuning runs
+// and, for the hop, LDS staging of the input window for the best of these)
+// with HIP events on the caller's stream, keeps the one with the lowest
+// median time, and stores it in a flat JSON object
+// {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds", ...} that later
+// runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
 #include <cstring>
@@ -44,28 +45,29 @@ Tuner::Tuner(const char *p)
 }
 
 // On a hit the stored fields replace those of `out`; an entry without the
-// third or fourth field keeps out.stream_links or out.xcd_slab.
+// third, fourth or fifth field keeps out.stream_links, out.xcd_slab or out.lds.
 bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) const
 {
     auto it = cache.find(key);
     if (it == cache.end()) return false;
-    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab;
-    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d", &b, &k, &st, &sl);
+    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab, ld = out.lds;
+    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld);
     if (n < 2) return false;
     if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1) ||
-        !(sl >= -1 && sl <= 1))
+        !(sl >= -1 && sl <= 1) || !(ld == 0 || ld == 1))
         return false;
     out.block = b;
     out.rhs_per_thread = k;
     out.stream_links = st;
     out.xcd_slab = sl;
+    out.lds = ld;
     return true;
 }
 
 void Tuner::store(const std::string &key, const LaunchShape &v)
 {
     cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread) + "," +
-                 std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab);
+                 std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab) + "," + std::to_string(v.lds);
 }
 
 void Tuner::save() const
@@ -174,7 +176,17 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // the candidates use the map the lattice shape selects; try the other
     LaunchShape flip = best_shape;
     flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
-    if (time_shape(flip) < best) best_shape = flip;
+    const float tf = time_shape(flip);
+    if (tf < best) {
+        best = tf;
+        best_shape = flip;
+    }
+    // then the hop with its x/y neighbours staged through LDS, where it is built and fits
+    LaunchShape staged = best_shape;
+    staged.lds = 1;
+    if (!is_dot && hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0 &&
+        time_shape(staged) < best)
+        best_shape = staged;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx.tuner->store(key, best_shape);

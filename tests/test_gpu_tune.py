@@ -42,8 +42,8 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
     assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
     for v in entries.values():
-        blk, k, st, sl = (int(t) for t in v.split(","))
-        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1)
+        blk, k, st, sl, ld = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1) and ld in (0, 1)
 
     # the persistent multi-lattice solve tunes its resident blocks per compute unit
     tuned = lqs.Context(0, tune_cache=cache, tuning=True)
@@ -172,3 +172,45 @@ def test_xcd_maps_give_identical_results(tmp_path):
     assert np.array_equal(a3, b3) and np.array_equal(a1, b1)
     assert ai == bi and np.array_equal(ax, bx)
     assert rel(a1, oracle.dslash(dims, U, srcs[0], 0)) <= 1e-14
+
+
+@pytest.mark.parametrize("dims", [(6, 8, 10, 12), (2, 4, 2, 6)])
+def test_lds_staged_hop_is_bit_identical(tmp_path, dims):
+    """The hop whose x and y neighbours come from an LDS window of the block's input sites
+    (other neighbours and the periodic wraps from memory) equals the plain hop to rounding (the
+    two kernels are compiled separately and may contract multiply-adds differently), for one
+    and several right-hand sides per thread, in every precision; both match the oracle."""
+    U = synth.gauge(dims, "haar", seed=97)
+    srcs = np.stack([synth.source(dims, 1, seed=970 + k) for k in range(3)])
+    cache = str(tmp_path / "tune.json")
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    g = gauge(tuned, dims, U)
+    for prec in (lqs.F64, lqs.F32, lqs.F16):
+        lqs.dslash_apply(tuned, g, field(tuned, dims, srcs, 1, prec))
+        lqs.dslash_apply(tuned, g, field(tuned, dims, srcs[0], 1, prec))
+    tuned.close()
+    entries = json.load(open(cache))
+    keys = [k for k in entries if "|hop|" in k]
+    assert len(keys) >= 6
+    outs = []
+    for ld in (0, 1):
+        for k in keys:
+            entries[k] = "64,1,0,-1,%d" % ld if k.endswith("|n1") else "64,2,1,0,%d" % ld
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        gg = gauge(ctx, dims, U)
+        res = []
+        for prec in (lqs.F64, lqs.F32, lqs.F16):
+            res.append(lex_of(ctx, lqs.dslash_apply(ctx, gg, field(ctx, dims, srcs, 1, prec)), squeeze=False))
+            res.append(lex_of(ctx, lqs.dslash_apply(ctx, gg, field(ctx, dims, srcs[0], 1, prec))))
+            res.append(lex_of(ctx, lqs.dslash_dagger(ctx, gg, field(ctx, dims, srcs, 1, prec)), squeeze=False))
+        outs.append(res)
+        ctx.close()
+    bounds = [1e-15] * 3 + [1e-6] * 3 + [2e-3] * 3  # F64, F32, F16 (storage rounding of the output)
+    for a, b, bound in zip(outs[0], outs[1], bounds):
+        assert rel(b, a) <= bound
+    for k in range(3):
+        want = oracle.dslash(dims, U, srcs[k], 0)
+        assert rel(outs[1][0][k], want) <= 1e-12 and rel(outs[1][3][k], want) <= 2e-6
+        assert rel(outs[1][6][k], want) <= 4e-3
