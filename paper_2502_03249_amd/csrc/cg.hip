@@ -131,12 +131,17 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
         act[j] = blk[j] && valid;
         any |= blk[j];
     }
-    if (!any) return;
+    if (!any) return;  // uniform over the block
+    extern __shared__ __align__(16) char win[];
+    int w0 = 0, wlen = 0;
+    const int wstride = lds_window_stride(g, P);
+    if (LF & LF_LDS)
+        stage_block_window<P, K>(g, tile * blockDim.x, t + r0 * stride, stride, blk, win, wstride, w0, wlen);
     double dot[K];
     V3<T> acc[K];
     if (valid) {
         const Site s = decode(g, cb, 0);
-        hop_site<P, R, K, LF>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc);
+        hop_site<P, R, K, LF>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc, win, wstride, w0, wlen);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -429,19 +434,23 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
     const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
     const double m2 = v.mass * v.mass;
+    const size_t lds = hop_lds_bytes(g, P, sh.rhs_per_thread, sh, L.temporal != 0);
 #define LQS_ND(K, LF)                                                                                             \
-    hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), 0, s, g, L, (const char *)v.t,     \
+    hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), lds, s, g, L, (const char *)v.t,   \
                        (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G, tpx)
 #define LQS_ND_LF(LF)                                                                                            \
     if (sh.rhs_per_thread == 1) LQS_ND(1, LF);                                                                   \
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \
     else LQS_ND(4, LF)
-    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0);
+    const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
     switch (lf) {
     case 0: LQS_ND_LF(0); break;
     case LF_TEMPORAL: LQS_ND_LF(LF_TEMPORAL); break;
     case LF_STREAM: LQS_ND_LF(LF_STREAM); break;
-    default: LQS_ND_LF(LF_TEMPORAL | LF_STREAM); break;
+    case LF_TEMPORAL | LF_STREAM: LQS_ND_LF(LF_TEMPORAL | LF_STREAM); break;
+    case LF_LDS: LQS_ND_LF(LF_LDS); break;
+    case LF_LDS | LF_STREAM: LQS_ND_LF(LF_LDS | LF_STREAM); break;
+    default: throw Error(LQS_EINVAL, "unexpected link flags");
     }
 #undef LQS_ND_LF
 #undef LQS_ND

@@ -34,19 +34,8 @@ __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity,
     if (!any) return;  // uniform over the block
     extern __shared__ __align__(16) char win[];
     int w0 = 0, wlen = 0;
-    const int wstride = (int)(spinor_bytes_per_site(P) * (blockDim.x + g.n[0] + 2));
-    if (LF & LF_LDS) {
-        // x and y neighbours of [c0, c0 + B) lie in [c0 - Nx/2 - 1, c0 + B + Nx/2 + 1)
-        // except across periodic boundaries, which are read from memory
-        const int h = g.n[0] / 2 + 1;
-        w0 = c0 - h > 0 ? c0 - h : 0;
-        const int w1 = c0 + (int)blockDim.x + h < g.vh ? c0 + (int)blockDim.x + h : g.vh;
-        wlen = w1 - w0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (active[j]) stage_window<P>(in + (r0 + j) * in_stride, g.vh, win + j * wstride, w0, wlen);
-        __syncthreads();
-    }
+    const int wstride = lds_window_stride(g, P);
+    if (LF & LF_LDS) stage_block_window<P, K>(g, c0, in + r0 * in_stride, in_stride, active, win, wstride, w0, wlen);
     if (cb >= g.vh) return;
     const Site s = decode(g, cb, parity);
     V3<T> acc[K];

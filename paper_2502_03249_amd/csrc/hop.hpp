@@ -103,6 +103,29 @@ template <> __device__ __forceinline__ void stage_window<F16>(const char *src, i
     for (int i = threadIdx.x; i < wlen; i += blockDim.x) ((uint4 *)dst)[i] = ((const uint4 *)src)[w0 + i];
 }
 
+// LF_LDS staging for the block whose sites start at c0: the x and y neighbours
+// of [c0, c0 + B) lie in [c0 - Nx/2 - 1, c0 + B + Nx/2 + 1) except across
+// periodic boundaries (read from memory).  Copies that window of every side j
+// with stage[j] set (block-uniform) into win + j * wstride and waits for the
+// block; returns the window as [w0, w0 + wlen).
+__device__ __forceinline__ int lds_window_stride(const Geom &g, int prec)
+{
+    return (int)(spinor_bytes_per_site(prec) * (blockDim.x + g.n[0] + 2));
+}
+template <int P, int K>
+__device__ __forceinline__ void stage_block_window(const Geom &g, int c0, const char *in, int64_t in_stride,
+                                                   const bool *stage, char *win, int wstride, int &w0, int &wlen)
+{
+    const int h = g.n[0] / 2 + 1;
+    w0 = c0 - h > 0 ? c0 - h : 0;
+    const int w1 = c0 + (int)blockDim.x + h < g.vh ? c0 + (int)blockDim.x + h : g.vh;
+    wlen = w1 - w0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (stage[j]) stage_window<P>(in + j * in_stride, g.vh, win + j * wstride, w0, wlen);
+    __syncthreads();
+}
+
 // LF_LDS: the x and y neighbours of a block's sites come from an LDS window
 // (win: right-hand side 0; win_stride bytes per side; sites [w0, w0 + wlen)).
 template <int P, int R, int K, int LF = 0>

@@ -3,7 +3,7 @@
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
 // thread x cached or streaming link loads, then the other block -> XCD map
-// and, for the hop, LDS staging of the input window for the best of these)
+// and LDS staging of the input window for the best of these)
 // with HIP events on the caller's stream, keeps the one with the lowest
 // median time, and stores it in a flat JSON object
 // {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds", ...} that later
@@ -184,8 +184,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // then the hop with its x/y neighbours staged through LDS, where it is built and fits
     LaunchShape staged = best_shape;
     staged.lds = 1;
-    if (!is_dot && hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0 &&
-        time_shape(staged) < best)
+    if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0 && time_shape(staged) < best)
         best_shape = staged;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

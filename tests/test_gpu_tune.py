@@ -214,3 +214,39 @@ def test_lds_staged_hop_is_bit_identical(tmp_path, dims):
         want = oracle.dslash(dims, U, srcs[k], 0)
         assert rel(outs[1][0][k], want) <= 1e-12 and rel(outs[1][3][k], want) <= 2e-6
         assert rel(outs[1][6][k], want) <= 4e-3
+
+
+def test_lds_staged_normal_kernel_in_cg(tmp_path):
+    """A multi-vector mixed-precision CG whose hop and fused normal kernel both stage their
+    input through LDS converges to the FP64 true residual, column by column, and agrees with
+    the unstaged solve to the CG tolerance."""
+    dims, mass = (6, 8, 10, 12), 0.1
+    U = synth.gauge(dims, "smooth", seed=98, eps=0.3)
+    b = np.stack([synth.source(dims, 0, seed=980 + k) for k in range(3)])
+    cache = str(tmp_path / "tune.json")
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    g = gauge(tuned, dims, U)
+    bf = field(tuned, dims, b, 0)
+    lqs.cg_solve(tuned, [(g, mass, bf, bf.like().zero_())], tol=1e-10, inner_prec=lqs.F32, reliable_interval=50)
+    tuned.close()
+    entries = json.load(open(cache))
+    keys = [k for k in entries if ("|hop|" in k or "|normal_dot|" in k) and k.endswith("|n3")]
+    assert len(keys) == 2
+    xs = []
+    for ld in (0, 1):
+        for k in keys:
+            entries[k] = "64,2,0,-1,%d" % ld
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        gg = gauge(ctx, dims, U)
+        bb = field(ctx, dims, b, 0)
+        xx = bb.like().zero_()
+        st = lqs.cg_solve(ctx, [(gg, mass, bb, xx)], tol=1e-10, inner_prec=lqs.F32, reliable_interval=50)
+        assert all(s_["status"] == 0 for s_ in st)
+        x = lex_of(ctx, xx, squeeze=False)
+        for k in range(3):
+            assert oracle.true_residual(dims, U, mass, b[k], x[k]) <= 1e-10
+        xs.append(x)
+        ctx.close()
+    assert rel(xs[1], xs[0]) <= (mass ** 2 + 64) / mass ** 2 * 2e-10
