@@ -120,8 +120,11 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     void *in = ctx.workspace("tune.in", fb);
     void *out = ctx.workspace("tune.out", fb);
     void *aux = ctx.workspace("tune.aux", fb);
-    LQS_HIP(hipMemsetAsync(in, 0, fb, s));
-    LQS_HIP(hipMemsetAsync(aux, 0, fb, s));
+    // Non-zero, finite inputs in every precision (bytes 0x3C: binary16 1.06, FP32 0.0115,
+    // FP64 1.6e-18): an all-zero FP16 site takes a shorter store path and would flatter
+    // the shapes tried on it.
+    LQS_HIP(hipMemsetAsync(in, 0x3C, fb, s));
+    LQS_HIP(hipMemsetAsync(aux, 0x3C, fb, s));
     CgVectors v{};
     CgState *st = nullptr;
     std::vector<CgState> tmpl(nrhs);
@@ -164,28 +167,29 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
         std::sort(t.begin(), t.end());
         return t[t.size() / 2];
     };
-    float best = 1e30f;
+    // A shape replaces the current best only when it is faster by more than
+    // MARGIN: shapes within the run-to-run spread of a few percent would
+    // otherwise be picked by noise (measured: a 64-thread FP16 hop chosen
+    // this way made the 64^3 x 16 solve 1 % slower than the default).
+    constexpr float MARGIN = 0.98f;
     LaunchShape best_shape = default_hop_shape(L, nrhs);
-    for (const LaunchShape &c : candidates(nrhs)) {
+    float best = time_shape(best_shape);
+    auto consider = [&](const LaunchShape &c) {
         const float med = time_shape(c);
-        if (med < best) {
+        if (med < MARGIN * best) {
             best = med;
             best_shape = c;
         }
-    }
+    };
+    for (const LaunchShape &c : candidates(nrhs)) consider(c);
     // the candidates use the map the lattice shape selects; try the other
     LaunchShape flip = best_shape;
     flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
-    const float tf = time_shape(flip);
-    if (tf < best) {
-        best = tf;
-        best_shape = flip;
-    }
-    // then the hop with its x/y neighbours staged through LDS, where it is built and fits
+    consider(flip);
+    // then the kernel with its x/y neighbours staged through LDS, where it is built and fits
     LaunchShape staged = best_shape;
     staged.lds = 1;
-    if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0 && time_shape(staged) < best)
-        best_shape = staged;
+    if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0) consider(staged);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx.tuner->store(key, best_shape);
