@@ -91,7 +91,7 @@ def traffic_for(kernel_key, launches_sites):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": a.gpus}))
         sys.exit(2)
     import numpy as np
@@ -369,8 +369,10 @@ def run_suite(a):
         torch.cuda.synchronize()
         return s.elapsed_time(e) / reps
 
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    ctx = lqs.Context(0, tune_cache=os.path.join(ROOT, "gpurun_out", "tune_suite.json"))
+    import tempfile
+    # the suite's tuned shapes persist across sections (and runs) in this JSON cache
+    tune_cache = os.environ.get("LQS_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "lqs_tune_suite.json"))
+    ctx = lqs.Context(0, tune_cache=tune_cache)
     only = set(a.suite_only.split(",")) if a.suite_only else None
 
     def want(name):
