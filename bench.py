@@ -674,6 +674,28 @@ def run_suite(a):
         _, st4, it4, tr4 = oracle.cg((4, 4, 4, 4), U4, 0.1, b4, tol=TOL)
         emit({"suite": "oracle_cg_4x4", "s": round(time.perf_counter() - t0, 4), "iters": it4, "true_res": tr4,
               "threads": nthr})
+        # the oracle's whole FP64 CG on the 32^3x8 (m 0.02) and 24^4 (m 0.05) systems, all threads,
+        # beside the GPU's FP64 and mixed solves of the same systems
+        for dh, mh, us, bs in (((32, 32, 32, 8), 0.02, 1001, 2001), ((24, 24, 24, 24), 0.05, 1004, 2004)):
+            Uh = synth.gauge(dh, "smooth", seed=us, eps=0.3)
+            bh = synth.source(dh, 0, seed=bs)
+            t0 = time.perf_counter()
+            _, _, ith, trh = oracle.cg(dh, Uh, mh, bh, tol=TOL)
+            t_or = time.perf_counter() - t0
+            gh = lqs.Gauge(ctx, dh, torch.from_numpy(Uh).to(dev), lqs.FMT_ALL)
+            bf = lqs.Field.from_lex(ctx, torch.from_numpy(bh).to(dev), 0)
+            xg = bf.like()
+            gpu = {}
+            for name, prec, rc in (("fp64", lqs.F64, 18), ("f16_mixed", lqs.F16, 12)):
+                lqs.cg_solve(ctx, [(gh, mh, bf, xg.zero_())], tol=TOL, inner_prec=prec, inner_recon=rc)
+                gpu[name] = timed(lambda: lqs.cg_solve(ctx, [(gh, mh, bf, xg.zero_())], tol=TOL, inner_prec=prec,
+                                                       inner_recon=rc), 2)
+            emit({"suite": "oracle_cg", "dims": dh, "mass": mh, "oracle_s": round(t_or, 3), "oracle_iters": ith,
+                  "oracle_true_res": trh, "threads": nthr, "gpu_fp64_s": round(gpu["fp64"], 5),
+                  "gpu_f16_mixed_s": round(gpu["f16_mixed"], 5),
+                  "speedup_gpu_fp64": round(t_or / gpu["fp64"], 1)})
+            gh.close()
+            del Uh, bh
 
     # 8. HMC on 24^4 (beta 5.5, m 0.05, tau 1): the plaquette force kernel alone, and whole
     #    trajectories with FP64 and mixed-precision solves (warm-started), Omelyan, 10 steps
