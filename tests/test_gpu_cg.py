@@ -162,3 +162,22 @@ def test_graph_replay_equals_eager(ctx, prec, recon, nrhs):
         assert np.array_equal(x, ref[0]), k
     for k in range(nrhs):
         assert oracle.true_residual(dims, U, mass, b[k], ref[0][k]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [lqs.F16, lqs.F32])
+def test_reliable_updates_every_chunk_hand_off_to_the_18_real_check(ctx, prec):
+    """A 12-real mixed solve with a reliable update due at every opportunity: the periodic
+    updates run on the FP64 12-real links. Near the end one of them meets the target and hands
+    the solve, still pending, to the check on the stored 18-real links. The check alone declares
+    convergence, and the reported residual agrees with the oracle's on the original links."""
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "smooth", seed=141, eps=0.3)
+    b = synth.source(dims, 0, seed=142)
+    for delta in (0.9, 0.0):
+        x, st = _solve(ctx, dims, U, mass, b, inner_prec=prec, inner_recon=12, reliable_interval=1,
+                       reliable_delta=delta)
+        assert st[0]["status"] == 0, st
+        assert st[0]["reliable_updates"] >= 10
+        tr = oracle.true_residual(dims, U, mass, b, x)
+        assert tr <= 1e-10
+        assert abs(tr - st[0]["true_rel_residual"]) <= 1e-13
