@@ -434,7 +434,7 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
     const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
     const double m2 = v.mass * v.mass;
-    const size_t lds = hop_lds_bytes(g, P, sh.rhs_per_thread, sh, L.temporal != 0);
+    const size_t lds = hop_lds_bytes(g, P, sh.rhs_per_thread, sh);
 #define LQS_ND(K, LF)                                                                                             \
     hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), lds, s, g, L, (const char *)v.t,   \
                        (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G, tpx)
@@ -450,7 +450,8 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     case LF_TEMPORAL | LF_STREAM: LQS_ND_LF(LF_TEMPORAL | LF_STREAM); break;
     case LF_LDS: LQS_ND_LF(LF_LDS); break;
     case LF_LDS | LF_STREAM: LQS_ND_LF(LF_LDS | LF_STREAM); break;
-    default: throw Error(LQS_EINVAL, "unexpected link flags");
+    case LF_LDS | LF_TEMPORAL: LQS_ND_LF(LF_LDS | LF_TEMPORAL); break;
+    default: LQS_ND_LF(LF_LDS | LF_TEMPORAL | LF_STREAM); break;
     }
 #undef LQS_ND_LF
 #undef LQS_ND

@@ -60,7 +60,7 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
     const int tiles = (g.vh + sh.block - 1) / sh.block, G = (nrhs + K - 1) / K;
     const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
     const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
-    const size_t lds = hop_lds_bytes(g, P, K, sh, L.temporal != 0);
+    const size_t lds = hop_lds_bytes(g, P, K, sh);
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
 #define LQS_HOP(DAG, LF)                                                                                         \
     hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), lds, s, g, L, parity, nrhs,          \
@@ -75,7 +75,8 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
     case LF_TEMPORAL | LF_STREAM: LQS_HOP_LF(LF_TEMPORAL | LF_STREAM); break;
     case LF_LDS: LQS_HOP_LF(LF_LDS); break;
     case LF_LDS | LF_STREAM: LQS_HOP_LF(LF_LDS | LF_STREAM); break;
-    default: throw Error(LQS_EINVAL, "unexpected link flags");
+    case LF_LDS | LF_TEMPORAL: LQS_HOP_LF(LF_LDS | LF_TEMPORAL); break;
+    default: LQS_HOP_LF(LF_LDS | LF_TEMPORAL | LF_STREAM); break;
     }
 #undef LQS_HOP_LF
 #undef LQS_HOP

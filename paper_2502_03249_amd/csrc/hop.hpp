@@ -72,11 +72,11 @@ __device__ __forceinline__ bool gate_open(const CgState *gate, int gate_mode, in
 }
 
 // LDS bytes of the staged input window of a hop launch: K sides of B + Nx + 2
-// sites; 0 (no staging) unless the shape asks for it, the links are not in
-// temporal gauge (that variant is not built) and the window fits in 64 KiB.
-inline size_t hop_lds_bytes(const Geom &g, int prec, int K, const LaunchShape &sh, bool temporal = false)
+// sites; 0 (no staging) unless the shape asks for it and the window fits in
+// 64 KiB.
+inline size_t hop_lds_bytes(const Geom &g, int prec, int K, const LaunchShape &sh)
 {
-    if (!sh.lds || temporal) return 0;
+    if (!sh.lds) return 0;
     const size_t b = (size_t)K * spinor_bytes_per_site(prec) * (sh.block + g.n[0] + 2);
     return b <= 65536 ? b : 0;
 }

@@ -189,7 +189,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // then the kernel with its x/y neighbours staged through LDS, where it is built and fits
     LaunchShape staged = best_shape;
     staged.lds = 1;
-    if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged, L.temporal != 0) > 0) consider(staged);
+    if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged) > 0) consider(staged);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx.tuner->store(key, best_shape);

@@ -250,3 +250,38 @@ def test_lds_staged_normal_kernel_in_cg(tmp_path):
         xs.append(x)
         ctx.close()
     assert rel(xs[1], xs[0]) <= (mass ** 2 + 64) / mass ** 2 * 2e-10
+
+
+def test_lds_staged_temporal_gauge_hop(tmp_path):
+    """LDS staging combined with the temporal-gauge hop (unit t-links by site index): equal to
+    the unstaged temporal hop to rounding and to the oracle on the gauge-fixed links."""
+    dims = (4, 6, 8, 10)  # 96-site time slices: wavefronts straddle slices
+    U = synth.gauge(dims, "haar", seed=99)
+    ctx0 = lqs.Context(0)
+    Uf = lqs.gauge_fix_temporal(ctx0, dims, torch.from_numpy(U).to("cuda"))[0].cpu().numpy()
+    ctx0.close()
+    srcs = np.stack([synth.source(dims, 1, seed=990 + k) for k in range(3)])
+    cache = str(tmp_path / "tune.json")
+    tuned = lqs.Context(0, tune_cache=cache, tuning=True)
+    g = lqs.Gauge(tuned, dims, torch.from_numpy(Uf).to("cuda"), lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+    for prec in (lqs.F64, lqs.F32):
+        lqs.dslash_apply(tuned, g, field(tuned, dims, srcs, 1, prec), recon=12)
+    tuned.close()
+    entries = json.load(open(cache))
+    keys = [k for k in entries if "|hop_tg|" in k]
+    assert len(keys) == 2
+    outs = []
+    for ld in (0, 1):
+        for k in keys:
+            entries[k] = "64,2,1,0,%d" % ld
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        gg = lqs.Gauge(ctx, dims, torch.from_numpy(Uf).to("cuda"), lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+        outs.append([lex_of(ctx, lqs.dslash_apply(ctx, gg, field(ctx, dims, srcs, 1, prec), recon=12),
+                            squeeze=False) for prec in (lqs.F64, lqs.F32)])
+        ctx.close()
+    assert rel(outs[1][0], outs[0][0]) <= 1e-15 and rel(outs[1][1], outs[0][1]) <= 1e-6
+    for k in range(3):
+        want = oracle.dslash(dims, Uf, srcs[k], 0)
+        assert rel(outs[1][0][k], want) <= 1e-12 and rel(outs[1][1][k], want) <= 2e-6
