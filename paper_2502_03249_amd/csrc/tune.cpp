@@ -186,7 +186,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LaunchShape flip = best_shape;
     flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
     consider(flip);
-    // then the kernel with its x/y neighbours staged through LDS, where it is built and fits
+    // then the kernel with its x/y neighbours staged through LDS, where the window fits
     LaunchShape staged = best_shape;
     staged.lds = 1;
     if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged) > 0) consider(staged);
