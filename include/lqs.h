@@ -198,7 +198,8 @@ typedef struct {
                                   of a mixed solve use those, the convergence check always
                                   the stored 18-real links                                   */
     int32_t reliable_interval; /* mixed: FP64 residual update every K iterations (0: 100)   */
-    double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r|| (0: 0.05)     */
+    double reliable_delta;     /* mixed: also when ||r|| < delta * max ||r||
+                                  (0: 0.02 with FP32 inner, 0.05 with FP16)                   */
     int32_t use_x0;            /* 1: start from x                                           */
     int32_t persistent;        /* 1: all problems in one cooperative launch (nrhs == 1)    */
 } lqs_cg_params;

@@ -718,7 +718,8 @@ struct CgRun {
         hs[0] = (CgState *)host;
         hs[1] = (CgState *)(host + sbytes);
         const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
-        const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.05) : 0.0;
+        const double delta =
+            mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : default_reliable_delta(prm.inner_prec)) : 0.0;
         for (int r = 0; r < nrhs; ++r) {
             CgState S{};
             S.stop2 = prm.tol * prm.tol;

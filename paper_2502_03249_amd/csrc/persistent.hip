@@ -429,7 +429,8 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
     uint32_t *abort_flag = (uint32_t *)(bars + PMAX_LAT);
     std::vector<CgState> init(nlat), hs(nlat);
     const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
-    const double delta = mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : 0.05) : 0.0;
+    const double delta =
+        mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : default_reliable_delta(prm.inner_prec)) : 0.0;
     for (auto &S : init) {
         S = CgState{};
         S.stop2 = prm.tol * prm.tol;
