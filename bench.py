@@ -307,7 +307,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "64^3x16 even-odd staggered CG to 1e-10, m=0.01, smooth links eps=0.3",
                    "dims": list(dims), "mass": MASS, "tol": TOL, "inner": a.inner, "recon": a.recon,
-                   "reliable_interval": a.reliable, "parallelism": "single GPU"},
+                   "reliable_interval": a.reliable,
+                   "reliable_delta": 0.05 if a.inner == "f16" else 0.02, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "cg": {"mixed_s": round(mixed_s, 5), "mixed_iters": stats[-1]["iters"],
