@@ -96,15 +96,25 @@ template <typename T> __device__ __forceinline__ void accum(V3<T> &acc, const V3
     }
 }
 
+// conj(x y - z w) with every product and sum in a fixed fused order, so that
+// each kernel that rebuilds a link gets the same bits whatever else it
+// contracts around the call.
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T> __device__ __forceinline__ Cx<T> conj_cross(Cx<T> x, Cx<T> y, Cx<T> z, Cx<T> w)
+{
+    const T re = fused(x.re, y.re, fused(-x.im, y.im, fused(-z.re, w.re, z.im * w.im)));
+    const T im = fused(x.re, y.im, fused(x.im, y.re, fused(-z.re, w.im, -(z.im * w.re))));
+    return {re, -im};
+}
+
 // Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
 template <typename T> __device__ __forceinline__ void rebuild_row2(M3<T> &u)
 {
-    Cx<T> a = csub(cmul(u.e[0][1], u.e[1][2]), cmul(u.e[0][2], u.e[1][1]));
-    Cx<T> b = csub(cmul(u.e[0][2], u.e[1][0]), cmul(u.e[0][0], u.e[1][2]));
-    Cx<T> c = csub(cmul(u.e[0][0], u.e[1][1]), cmul(u.e[0][1], u.e[1][0]));
-    u.e[2][0] = {a.re, -a.im};
-    u.e[2][1] = {b.re, -b.im};
-    u.e[2][2] = {c.re, -c.im};
+    u.e[2][0] = conj_cross(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
+    u.e[2][1] = conj_cross(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
+    u.e[2][2] = conj_cross(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
 }
 
 // ---------------------------------------------------------------------------

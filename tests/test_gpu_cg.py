@@ -136,6 +136,26 @@ def test_cg_full_size_benchmark_solve(ctx):
     assert abs(tr - st[0]["true_rel_residual"]) <= 1e-12
 
 
+def test_cg_full_size_sixteen_rhs(ctx):
+    """The largest block of independent solves at full size: 64^3 x 16, 16 right-hand sides,
+    FP32 12-real inner with FP64 reliable updates; the oracle recomputes the FP64 true residual
+    of sampled columns."""
+    dims, mass, nrhs = (64, 64, 64, 16), 0.01, 16
+    U = synth.gauge(dims, "smooth", seed=1002, eps=0.3)
+    b = np.stack([synth.source(dims, 0, seed=2300 + k) for k in range(nrhs)])
+    g = gauge(ctx, dims, U, lqs.fmt(lqs.F64, 18) | lqs.fmt(lqs.F64, 12) | lqs.fmt(lqs.F32, 12))
+    bf = field(ctx, dims, b, 0)
+    xf = bf.like().zero_()
+    st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=lqs.F32, inner_recon=12,
+                      reliable_interval=100)
+    assert len(st) == nrhs and all(s["status"] == 0 for s in st)
+    x = lex_of(ctx, xf, squeeze=False)
+    for k in (0, 9, nrhs - 1):
+        tr = oracle.true_residual(dims, U, mass, b[k], x[k])
+        assert tr <= 1e-10, (k, tr)
+        assert abs(tr - st[k]["true_rel_residual"]) <= 1e-12, k
+
+
 @pytest.mark.parametrize("prec,recon,nrhs", [(lqs.F64, 18, 1), (lqs.F16, 12, 1), (lqs.F32, 12, 3)])
 def test_graph_replay_equals_eager(ctx, prec, recon, nrhs):
     """Solves whose iteration rounds are captured once into a HIP graph and replayed (with the
