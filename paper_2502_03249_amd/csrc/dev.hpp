@@ -56,30 +56,46 @@ template <typename T> __device__ __forceinline__ V3<T> vzero()
     return v;
 }
 
-// U v
+// The products of the operator are written as explicit fused multiply-adds
+// in one fixed order, so that every kernel variant built on them (vectors per
+// thread, cached or streaming loads, LDS staging) computes the same bits.
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// U v: each component is sum_b u_ab v_b, accumulated b = 0, 1, 2
 template <typename T> __device__ __forceinline__ V3<T> mv(const M3<T> &u, const V3<T> &v)
 {
     V3<T> w;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        Cx<T> s = cmul(u.e[a][0], v.c[0]);
-        s = cadd(s, cmul(u.e[a][1], v.c[1]));
-        s = cadd(s, cmul(u.e[a][2], v.c[2]));
-        w.c[a] = s;
+        T re = -(u.e[a][0].im * v.c[0].im), im = u.e[a][0].im * v.c[0].re;
+        re = fused(u.e[a][0].re, v.c[0].re, re);
+        im = fused(u.e[a][0].re, v.c[0].im, im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            re = fused(-u.e[a][b].im, v.c[b].im, fused(u.e[a][b].re, v.c[b].re, re));
+            im = fused(u.e[a][b].im, v.c[b].re, fused(u.e[a][b].re, v.c[b].im, im));
+        }
+        w.c[a] = {re, im};
     }
     return w;
 }
 
-// U^dag v
+// U^dag v: each component is sum_b conj(u_ba) v_b, accumulated b = 0, 1, 2
 template <typename T> __device__ __forceinline__ V3<T> mdv(const M3<T> &u, const V3<T> &v)
 {
     V3<T> w;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        Cx<T> s = cjmul(u.e[0][a], v.c[0]);
-        s = cadd(s, cjmul(u.e[1][a], v.c[1]));
-        s = cadd(s, cjmul(u.e[2][a], v.c[2]));
-        w.c[a] = s;
+        T re = u.e[0][a].im * v.c[0].im, im = -(u.e[0][a].im * v.c[0].re);
+        re = fused(u.e[0][a].re, v.c[0].re, re);
+        im = fused(u.e[0][a].re, v.c[0].im, im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            re = fused(u.e[b][a].im, v.c[b].im, fused(u.e[b][a].re, v.c[b].re, re));
+            im = fused(-u.e[b][a].im, v.c[b].re, fused(u.e[b][a].re, v.c[b].im, im));
+        }
+        w.c[a] = {re, im};
     }
     return w;
 }
@@ -96,12 +112,7 @@ template <typename T> __device__ __forceinline__ void accum(V3<T> &acc, const V3
     }
 }
 
-// conj(x y - z w) with every product and sum in a fixed fused order, so that
-// each kernel that rebuilds a link gets the same bits whatever else it
-// contracts around the call.
-__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
+// conj(x y - z w), fused in a fixed order like the products above.
 template <typename T> __device__ __forceinline__ Cx<T> conj_cross(Cx<T> x, Cx<T> y, Cx<T> z, Cx<T> w)
 {
     const T re = fused(x.re, y.re, fused(-x.im, y.im, fused(-z.re, w.re, z.im * w.im)));
