@@ -189,6 +189,22 @@ def test_cg_matches_dense_solve():
     assert np.abs(on_parity(x, SMALL, 1)).max() == 0.0
 
 
+def test_true_residual_from_dense_operator():
+    """||b - M x|| / ||b|| on even fields equals the same norm formed with the dense M (itself
+    pinned to the dense D above), for an arbitrary x, and vanishes to rounding at the dense solution."""
+    mass = 0.1
+    U = synth.gauge(SMALL, "haar", seed=1000)
+    b = synth.source(SMALL, 0, seed=2000)
+    x = on_parity(_rand_field(SMALL, 7), SMALL, 0)
+    M, idx = _dense_even(SMALL, U, mass)
+    be, xe = b.reshape(-1)[idx], x.reshape(-1)[idx]
+    want = np.linalg.norm(be - M @ xe) / np.linalg.norm(be)
+    assert abs(oracle.true_residual(SMALL, U, mass, b, x) - want) <= 1e-12 * want
+    xs = np.zeros(b.size, np.complex128)
+    xs[idx] = np.linalg.solve(M, be)
+    assert oracle.true_residual(SMALL, U, mass, b, xs.reshape(b.shape)) <= 1e-13
+
+
 def test_cg_plane_wave_exact_solution():
     """Free field: the solution for a plane-wave source is f_e / (m^2 + 4 sum sin^2 p)."""
     dims, mass = (8, 8, 8, 8), 0.05
