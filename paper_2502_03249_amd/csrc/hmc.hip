@@ -148,27 +148,61 @@ __global__ void __launch_bounds__(1024) hmc_finalize(const double *partials, int
 // staple sums meet in LDS, and the slot-0 wave forms U V and its traceless
 // anti-Hermitian part.  A block covers 64 consecutive sites of one mu (one
 // wave per slot), so every load of a wave is a contiguous run of links.
+// PK: the links are read from the word-major FP64 18-real copy of the same
+// links (block 2 mu + parity, word k of checkerboard site cb at k * pitch +
+// cb), where a wave's load of one word is two contiguous 512-byte runs
+// instead of 64 loads 144 bytes apart; the output stays canonical.
 constexpr int GF_SITES = 64;
 
-__global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int vol, const double2 *U, double beta,
-                                                                   double coeff, int mode, double2 *out)
+template <bool PK>
+__device__ __forceinline__ Mat gf_link(const double2 *U, int vol, const double2 *P, int pitch, int mu, int parity,
+                                       int lex)
+{
+    if constexpr (!PK) return mat_load(link_at(U, vol, mu, lex));
+    const double2 *b = P + (int64_t)(2 * mu + parity) * 9 * pitch + (lex >> 1);
+    Mat m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 d = b[(int64_t)k * pitch];
+        m.e[k / 3][k % 3] = {d.x, d.y};
+    }
+    return m;
+}
+
+template <bool PK>
+__global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int vol, const double2 *U, const double2 *P,
+                                                                   int pitch, double beta, double coeff, int mode,
+                                                                   double2 *out)
 {
     __shared__ double2 part[3][9][GF_SITES];
     const int mu = blockIdx.y;
     const int slot = threadIdx.x / GF_SITES, lane = threadIdx.x % GF_SITES;
     const int x = blockIdx.x * GF_SITES + lane;
     const bool valid = x < vol;
+    // parity of x; its one-step neighbours have the other parity, x + mu - nu the same
+    int par = 0;
+    if (PK && valid) {
+        int l = x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            par += l % g.n[i];
+            l /= g.n[i];
+        }
+        par &= 1;
+    }
     if (valid) {
         const int nu = slot + (slot >= mu ? 1 : 0);
         const int xm = nbr(g, x, mu, 1);
         // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
         const int xn = nbr(g, x, nu, 1);
-        Mat a = mat_mul<false, true>(mat_load(link_at(U, vol, nu, xm)), mat_load(link_at(U, vol, mu, xn)));
-        a = mat_mul<false, true>(a, mat_load(link_at(U, vol, nu, x)));
+        Mat a = mat_mul<false, true>(gf_link<PK>(U, vol, P, pitch, nu, par ^ 1, xm),
+                                     gf_link<PK>(U, vol, P, pitch, mu, par ^ 1, xn));
+        a = mat_mul<false, true>(a, gf_link<PK>(U, vol, P, pitch, nu, par, x));
         // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
         const int xd = nbr(g, x, nu, -1), xmd = nbr(g, xm, nu, -1);
-        Mat b = mat_mul<true, true>(mat_load(link_at(U, vol, nu, xmd)), mat_load(link_at(U, vol, mu, xd)));
-        b = mat_mul<false, false>(b, mat_load(link_at(U, vol, nu, xd)));
+        Mat b = mat_mul<true, true>(gf_link<PK>(U, vol, P, pitch, nu, par, xmd),
+                                    gf_link<PK>(U, vol, P, pitch, mu, par ^ 1, xd));
+        b = mat_mul<false, false>(b, gf_link<PK>(U, vol, P, pitch, nu, par ^ 1, xd));
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -190,7 +224,7 @@ __global__ void __launch_bounds__(3 * GF_SITES) gauge_force_kernel(Geom g, int v
             const double2 p0 = part[0][3 * i + j][lane], p1 = part[1][3 * i + j][lane], p2 = part[2][3 * i + j][lane];
             v.e[i][j] = {(p0.x + p1.x) + p2.x, (p0.y + p1.y) + p2.y};
         }
-    const Mat w = mat_mul<false, false>(mat_load(link_at(U, vol, mu, x)), v);
+    const Mat w = mat_mul<false, false>(gf_link<PK>(U, vol, P, pitch, mu, par, x), v);
     // TA(W) = (W - W^dag)/2 - tr(W - W^dag)/6
     Mat t;
 #pragma unroll
@@ -318,12 +352,20 @@ void launch_kinetic(Ctx &ctx, const Geom &g, const double *Q, double *out, int s
 }
 
 void launch_gauge_force(const Geom &g, const double *U, double beta, double coeff, int accumulate, double *out,
-                        hipStream_t s)
+                        hipStream_t s, const LinkRef *packed)
 {
     const int vol = 2 * g.vh;
     dim3 grid((vol + GF_SITES - 1) / GF_SITES, 4);
-    hipLaunchKernelGGL(gauge_force_kernel, grid, dim3(3 * GF_SITES), 0, s, g, vol, (const double2 *)U, beta, coeff,
-                       accumulate ? 1 : 0, (double2 *)out);
+    if (packed) {
+        LQS_REQUIRE(!packed->temporal && packed->pitch >= g.vh && packed->block_bytes == 144 * (int64_t)packed->pitch,
+                    LQS_EINVAL, "gauge force: packed links must be the plain FP64 18-real format");
+        hipLaunchKernelGGL(gauge_force_kernel<true>, grid, dim3(3 * GF_SITES), 0, s, g, vol, (const double2 *)U,
+                           (const double2 *)packed->base, (int)packed->pitch, beta, coeff, accumulate ? 1 : 0,
+                           (double2 *)out);
+    } else {
+        hipLaunchKernelGGL(gauge_force_kernel<false>, grid, dim3(3 * GF_SITES), 0, s, g, vol, (const double2 *)U,
+                           (const double2 *)nullptr, 0, beta, coeff, accumulate ? 1 : 0, (double2 *)out);
+    }
     LQS_HIP(hipGetLastError());
 }
 
@@ -453,7 +495,8 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
     // mom -= eps F / 2, the fermion part from chi on the current links; the
     // solve on the final links (last) also gives S_f at the end
     auto momentum = [&](double eps, bool have_chi, bool last) {
-        launch_gauge_force(g, U1, prm.beta, -0.5 * eps, 1, mom, s);
+        // with fermions the word-major FP64 18-real copy of U1 is current here
+        launch_gauge_force(g, U1, prm.beta, -0.5 * eps, 1, mom, s, ferm ? &L64 : nullptr);
         if (!ferm) return;
         if (!have_chi) solve(last);
         launch_hop_gated(g, L64, F64, 18, 0, 1, 1, chi, psx, nullptr, 0, sh, s);

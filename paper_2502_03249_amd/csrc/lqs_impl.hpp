@@ -234,8 +234,9 @@ void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lq
 // hmc.hip (canonical [4][V][3][3] complex128 links and momenta)
 void launch_gauge_action(Ctx &ctx, const Geom &g, const double *U, double beta, double *out, int slot, hipStream_t s);
 void launch_kinetic(Ctx &ctx, const Geom &g, const double *Q, double *out, int slot, hipStream_t s);
+// packed: optional word-major FP64 18-real copy of U (read instead of U)
 void launch_gauge_force(const Geom &g, const double *U, double beta, double coeff, int accumulate, double *out,
-                        hipStream_t s);
+                        hipStream_t s, const LinkRef *packed = nullptr);
 void launch_link_update(const Geom &g, double *U, const double *Q, double eps, hipStream_t s);
 void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, const double *pf, double u,
                          const lqs_hmc_params &prm, lqs_hmc_stats &st, double *proposal, double *phi_out,
