@@ -151,6 +151,13 @@ lqs_status lqs_field_pack(lqs_ctx *ctx, const int32_t dims[4], const double *lex
 /* native field -> lex; writes only the sites of in->parity, others untouched. */
 lqs_status lqs_field_unpack(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double *lex,
                             void *stream);
+/* As lqs_field_unpack, with every component multiplied in FP64 by the real
+ * number `scale` on the way out (finite, else LQS_EINVAL); scale = 1 is
+ * lqs_field_unpack.  Gives the source gradient 2 g M^-1 phi of the action
+ * phi^dag M^-1 phi (PyTorch's complex-gradient convention) from chi = M^-1 phi
+ * without arithmetic outside the library. */
+lqs_status lqs_field_unpack_scaled(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double scale,
+                                   double *lex, void *stream);
 
 /* out[2*r], out[2*r+1] = real and imaginary part of sum_sites a_r^dag b_r for
  * each right-hand side r (FP64 fields of one parity, nrhs each; out is a

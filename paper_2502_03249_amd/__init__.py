@@ -88,7 +88,7 @@ EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_cre
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
            "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
            "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal", "gauge_action", "gauge_force",
-           "link_update", "kinetic_energy", "hmc_trajectory", "lqs_set_graphs"]
+           "link_update", "kinetic_energy", "hmc_trajectory", "lqs_set_graphs", "lqs_field_unpack_scaled"]
 
 
 def lib():
@@ -113,6 +113,7 @@ def lib():
     L.lqs_gauge_fix_temporal.argtypes = [vp, i32p, vp, vp, vp, vp]
     L.lqs_field_pack.argtypes = [vp, i32p, vp, ctypes.POINTER(LqsField), vp]
     L.lqs_field_unpack.argtypes = [vp, i32p, ctypes.POINTER(LqsField), vp, vp]
+    L.lqs_field_unpack_scaled.argtypes = [vp, i32p, ctypes.POINTER(LqsField), d, vp, vp]
     L.dslash_apply.argtypes = [vp, vp, i32, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp]
     L.dslash_dagger.argtypes = [vp, vp, i32, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp]
     L.cg_solve.argtypes = [vp, i32, ctypes.POINTER(LqsProblem), ctypes.POINTER(LqsCgParams),
@@ -283,14 +284,19 @@ class Field:
         f._keep = lex
         return f
 
-    def to_lex(self, ctx, out=None, stream=None):
-        """Unpack into canonical complex128 (nrhs, Nt, Nz, Ny, Nx, 3), zero off this field's parity."""
+    def to_lex(self, ctx, out=None, stream=None, scale=None):
+        """Unpack into canonical complex128 (nrhs, Nt, Nz, Ny, Nx, 3), zero off this field's parity;
+        with scale, every value is multiplied by that real number inside the library."""
         nx, ny, nz, nt = self.dims
         if out is None:
             out = torch.zeros((self.nrhs, nt, nz, ny, nx, 3), dtype=torch.complex128, device=self.data.device)
         c = self.c()
-        _check(lib().lqs_field_unpack(ctx.handle, _dims(self.dims), ctypes.byref(c), ctypes.c_void_p(out.data_ptr()),
-                                      _stream(stream)))
+        if scale is None:
+            _check(lib().lqs_field_unpack(ctx.handle, _dims(self.dims), ctypes.byref(c),
+                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        else:
+            _check(lib().lqs_field_unpack_scaled(ctx.handle, _dims(self.dims), ctypes.byref(c), float(scale),
+                                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
 

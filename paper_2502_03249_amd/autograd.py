@@ -74,7 +74,7 @@ class StaggeredAction(torch.autograd.Function):
         g = float(grad_s)
         grad_phi = None
         if fctx.needs_input_grad[1]:
-            grad_phi = chi.to_lex(lqs_ctx)[0] * (2.0 * g)
+            grad_phi = chi.to_lex(lqs_ctx, scale=2.0 * g)[0]
         grad_links = None
         if fctx.needs_input_grad[0]:
             grad_links = fermion_force(lqs_ctx, gauge, chi, None, coeff=g, mode=0 if project else 1)

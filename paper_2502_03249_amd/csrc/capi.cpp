@@ -290,12 +290,19 @@ lqs_status lqs_field_pack(lqs_ctx *ctx, const int32_t dims[4], const double *lex
 
 lqs_status lqs_field_unpack(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double *lex, void *stream)
 {
+    return lqs_field_unpack_scaled(ctx, dims, in, 1.0, lex, stream);
+}
+
+lqs_status lqs_field_unpack_scaled(lqs_ctx *ctx, const int32_t dims[4], const lqs_field *in, double scale, double *lex,
+                                   void *stream)
+{
     return guard([&] {
         LQS_REQUIRE(ctx != nullptr, LQS_EINVAL, "ctx is NULL");
         check_dims(dims);
         check_ptr(lex, "lex");
         check_field(in, "in");
-        launch_field_unpack(make_geom(dims), *in, lex, as_stream(stream));
+        LQS_REQUIRE(std::isfinite(scale), LQS_EINVAL, "scale must be finite");
+        launch_field_unpack(make_geom(dims), *in, scale, lex, as_stream(stream));
     });
 }
 

@@ -465,7 +465,7 @@ void hmc_trajectory_impl(Ctx &ctx, const Geom &g, double *links, double *mom, co
         }
         if (phi_out) {
             LQS_HIP(hipMemsetAsync(phi_out, 0, sizeof(double) * 6 * (size_t)vol, s));
-            launch_field_unpack(g, lqs_field{phi, F64, 0, 1}, phi_out, s);
+            launch_field_unpack(g, lqs_field{phi, F64, 0, 1}, 1.0, phi_out, s);
         }
     }
     // chi = M^-1 phi on the current links (warm start from the previous chi if

@@ -164,7 +164,7 @@ void launch_pack_links(const Geom &g, const double *canon, int prec, int recon, 
 // the unit link at index vh of the two t-link blocks of a temporal-gauge format
 void launch_unit_link(const Geom &g, int prec, int recon, int64_t pitch, void *links, hipStream_t s);
 void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s);
-void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s);
+void launch_field_unpack(const Geom &g, const lqs_field &in, double scale, double *lex, hipStream_t s);
 void launch_convert(const Geom &g, int nrhs, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
 void launch_gauge_fix_temporal(const Geom &g, const double *links, double *out, double *G, hipStream_t s);
 double temporal_gauge_violation(Ctx &ctx, const Geom &g, const double *links, hipStream_t s);

@@ -96,7 +96,8 @@ __global__ void field_pack_kernel(Geom g, const double2 *lex, int parity, char *
 }
 
 template <int P>
-__global__ void field_unpack_kernel(Geom g, const char *in, int64_t rhs_stride, int parity, double2 *lex)
+__global__ void field_unpack_kernel(Geom g, const char *in, int64_t rhs_stride, int parity, double scale,
+                                    double2 *lex)
 {
     const int64_t V = 2 * (int64_t)g.vh;
     const int cb = blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,7 +107,7 @@ __global__ void field_unpack_kernel(Geom g, const char *in, int64_t rhs_stride, 
     const auto v = SpinorIO<P>::load(in + r * rhs_stride, g.vh, cb);
     double2 *dst = lex + 3 * (r * V + l);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dst[a] = make_double2((double)v.c[a].re, (double)v.c[a].im);
+    for (int a = 0; a < 3; ++a) dst[a] = make_double2(scale * (double)v.c[a].re, scale * (double)v.c[a].im);
 }
 
 void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, hipStream_t s)
@@ -125,19 +126,20 @@ void launch_field_pack(const Geom &g, const double *lex, const lqs_field &out, h
     LQS_HIP(hipGetLastError());
 }
 
-void launch_field_unpack(const Geom &g, const lqs_field &in, double *lex, hipStream_t s)
+// scale 1 leaves every value unchanged (an exact product)
+void launch_field_unpack(const Geom &g, const lqs_field &in, double scale, double *lex, hipStream_t s)
 {
     dim3 grid((g.vh + 255) / 256, in.nrhs);
     const int64_t stride = field_bytes(g, in.prec, 1);
     if (in.prec == F64)
         hipLaunchKernelGGL(field_unpack_kernel<F64>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
-                           in.parity, (double2 *)lex);
+                           in.parity, scale, (double2 *)lex);
     else if (in.prec == F32)
         hipLaunchKernelGGL(field_unpack_kernel<F32>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
-                           in.parity, (double2 *)lex);
+                           in.parity, scale, (double2 *)lex);
     else
         hipLaunchKernelGGL(field_unpack_kernel<F16>, grid, dim3(256), 0, s, g, (const char *)in.data, stride,
-                           in.parity, (double2 *)lex);
+                           in.parity, scale, (double2 *)lex);
     LQS_HIP(hipGetLastError());
 }
 

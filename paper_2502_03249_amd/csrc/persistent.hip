@@ -183,8 +183,8 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
         const double s = block_sum(loc);
         if (threadIdx.x == 0) L.part[0][tile] = s;
     }
-    if (!group_sync(gb, abort_flag, nb, gen)) goto out;
-    {
+    bool aborted = !group_sync(gb, abort_flag, nb, gen);
+    if (!aborted) {
         const double b2 = sum_partials(L.part[0], L.ntiles);
         if (threadIdx.x == 0) {
             S.b2 = b2;
@@ -198,7 +198,60 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
         __syncthreads();
     }
 
-    for (int trip = 0; trip < max_trips && S.phase == CG_RUNNING; ++trip) {
+    // FP64 residual of x + x_lo: t64 = D_oe (x + x_lo), then x += x_lo, x_lo = 0 and
+    // r = b - (m^2 x - D_eo t64); returns |r|^2 (false when a barrier aborted).
+    // store_r = false leaves r alone (measurement only).
+    auto fp64_residual = [&](bool store_r, double &r2) -> bool {
+        for (int tile = lb; tile < L.ntiles; tile += nb) {
+            const int cb = tile * BS + threadIdx.x;
+            if (cb >= vh) continue;
+            const Site s = decode(L.g, cb, 1);
+            const V3<double> acc = hop_site_fn<F64, 18>(L.g, L.hi, 1, s, cb, [&](int n) {
+                V3<double> v = SpinorIO<F64>::load(L.x, vh, n);
+                const V3<double> w = vcast<double>(SpinorIO<PA>::load(L.xlo, vh, n));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    v.c[a].re += w.c[a].re;
+                    v.c[a].im += w.c[a].im;
+                }
+                return v;
+            });
+            SpinorIO<F64>::store(L.t64, vh, cb, acc);
+        }
+        if (!group_sync(gb, abort_flag, nb, gen)) return false;
+        for (int tile = lb; tile < L.ntiles; tile += nb) {
+            const int cb = tile * BS + threadIdx.x;
+            double loc = 0.0;
+            if (cb < vh) {
+                const Site s = decode(L.g, cb, 0);
+                V3<double> acc;
+                const bool act = true;
+                hop_site<F64, 18, 1>(L.g, L.hi, 0, s, cb, L.t64, 0, &act, &acc);
+                V3<double> xv = SpinorIO<F64>::load(L.x, vh, cb);
+                const V3<double> lv = vcast<double>(SpinorIO<PA>::load(L.xlo, vh, cb));
+                const V3<double> bv = SpinorIO<F64>::load(L.b, vh, cb);
+                V3<double> rv;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    xv.c[a].re += lv.c[a].re;
+                    xv.c[a].im += lv.c[a].im;
+                    rv.c[a].re = bv.c[a].re - (L.m2 * xv.c[a].re - acc.c[a].re);
+                    rv.c[a].im = bv.c[a].im - (L.m2 * xv.c[a].im - acc.c[a].im);
+                    loc += rv.c[a].re * rv.c[a].re + rv.c[a].im * rv.c[a].im;
+                }
+                SpinorIO<F64>::store(L.x, vh, cb, xv);
+                SpinorIO<PA>::store(L.xlo, vh, cb, vzero<TA>());
+                if (store_r) SpinorIO<PA>::store(L.r, vh, cb, vcast<TA>(rv));
+            }
+            const double s = block_sum(loc);
+            if (threadIdx.x == 0) L.part[0][tile] = s;
+        }
+        if (!group_sync(gb, abort_flag, nb, gen)) return false;
+        r2 = sum_partials(L.part[0], L.ntiles);
+        return true;
+    };
+
+    for (int trip = 0; !aborted && trip < max_trips && S.phase == CG_RUNNING; ++trip) {
         // ---- H: t = D_oe (r + beta p)
         {
             const TA beta = (TA)S.beta;
@@ -210,7 +263,10 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
                 SpinorIO<P>::store(L.t, vh, cb, acc);
             }
         }
-        if (!group_sync(gb, abort_flag, nb, gen)) break;
+        if (!group_sync(gb, abort_flag, nb, gen)) {
+            aborted = true;
+            break;
+        }
 
         // ---- N: p = r + beta p, q = m^2 p - D_eo t, tile partials of <p, q>
         for (int tile = lb; tile < L.ntiles; tile += nb) {
@@ -235,7 +291,10 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
             const double s = block_sum(dot);
             if (threadIdx.x == 0) L.part[0][tile] = s;
         }
-        if (!group_sync(gb, abort_flag, nb, gen)) break;
+        if (!group_sync(gb, abort_flag, nb, gen)) {
+            aborted = true;
+            break;
+        }
         {
             const double pq = sum_partials(L.part[0], L.ntiles);
             if (threadIdx.x == 0) {
@@ -273,7 +332,10 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
                 if (threadIdx.x == 0) L.part[1][tile] = s;
             }
         }
-        if (!group_sync(gb, abort_flag, nb, gen)) break;
+        if (!group_sync(gb, abort_flag, nb, gen)) {
+            aborted = true;
+            break;
+        }
         {
             const double r2 = sum_partials(L.part[1], L.ntiles);
             if (threadIdx.x == 0) p_fin_update(S, r2);
@@ -281,60 +343,23 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
         }
         if (!S.reliable_pending) continue;
 
-        // ---- R1: t64 = D_oe (x + x_lo) in FP64
-        for (int tile = lb; tile < L.ntiles; tile += nb) {
-            const int cb = tile * BS + threadIdx.x;
-            if (cb >= vh) continue;
-            const Site s = decode(L.g, cb, 1);
-            const V3<double> acc = hop_site_fn<F64, 18>(L.g, L.hi, 1, s, cb, [&](int n) {
-                V3<double> v = SpinorIO<F64>::load(L.x, vh, n);
-                const V3<double> w = vcast<double>(SpinorIO<PA>::load(L.xlo, vh, n));
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    v.c[a].re += w.c[a].re;
-                    v.c[a].im += w.c[a].im;
-                }
-                return v;
-            });
-            SpinorIO<F64>::store(L.t64, vh, cb, acc);
+        // ---- R: the FP64 residual (x += x_lo, x_lo = 0, r = b - M x)
+        double r2 = 0.0;
+        if (!fp64_residual(true, r2)) {
+            aborted = true;
+            break;
         }
-        if (!group_sync(gb, abort_flag, nb, gen)) break;
-        // ---- R2: x += x_lo, x_lo = 0, r = b - (m^2 x - D_eo t64)
-        for (int tile = lb; tile < L.ntiles; tile += nb) {
-            const int cb = tile * BS + threadIdx.x;
-            double loc = 0.0;
-            if (cb < vh) {
-                const Site s = decode(L.g, cb, 0);
-                V3<double> acc;
-                const bool act = true;
-                hop_site<F64, 18, 1>(L.g, L.hi, 0, s, cb, L.t64, 0, &act, &acc);
-                V3<double> xv = SpinorIO<F64>::load(L.x, vh, cb);
-                const V3<double> lv = vcast<double>(SpinorIO<PA>::load(L.xlo, vh, cb));
-                const V3<double> bv = SpinorIO<F64>::load(L.b, vh, cb);
-                V3<double> rv;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    xv.c[a].re += lv.c[a].re;
-                    xv.c[a].im += lv.c[a].im;
-                    rv.c[a].re = bv.c[a].re - (L.m2 * xv.c[a].re - acc.c[a].re);
-                    rv.c[a].im = bv.c[a].im - (L.m2 * xv.c[a].im - acc.c[a].im);
-                    loc += rv.c[a].re * rv.c[a].re + rv.c[a].im * rv.c[a].im;
-                }
-                SpinorIO<F64>::store(L.x, vh, cb, xv);
-                SpinorIO<PA>::store(L.xlo, vh, cb, vzero<TA>());
-                SpinorIO<PA>::store(L.r, vh, cb, vcast<TA>(rv));
-            }
-            const double s = block_sum(loc);
-            if (threadIdx.x == 0) L.part[0][tile] = s;
-        }
-        if (!group_sync(gb, abort_flag, nb, gen)) break;
-        {
-            const double r2 = sum_partials(L.part[0], L.ntiles);
-            if (threadIdx.x == 0) p_fin_residual(S, r2);
-            __syncthreads();
-        }
+        if (threadIdx.x == 0) p_fin_residual(S, r2);
+        __syncthreads();
     }
-out:
+    // A group that stopped without its final FP64 check (breakdown, non-finite
+    // scalar, trip cap) still returns x = x + x_lo with its measured residual,
+    // as the multi-kernel solver does.  After an aborted barrier x is undefined.
+    if (!aborted && S.phase != CG_CONVERGED && S.phase != CG_MAXITER) {
+        double r2 = 0.0;
+        if (fp64_residual(false, r2) && threadIdx.x == 0) S.true_r2 = r2;
+        __syncthreads();
+    }
     if (lb == 0 && threadIdx.x == 0) st_out[lat] = S;
 }
 

@@ -34,3 +34,27 @@ def lex_of(ctx, f, squeeze=True):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def site_error_ratio(dims, got, want, src, out_parity):
+    """Largest per-site error of a hop, relative to what storage rounding can cause there.
+
+    For each output site x of parity out_parity: |got(x) - want(x)| / sum over the eight
+    neighbours y of |src(y)| (colour-vector 2-norms).  Every term of eq. (1) is an SU(3)
+    matrix (norm 1) times a neighbour vector, so rounding the links, the vectors and the
+    output to a format of unit roundoff u changes out(x) by at most a small multiple of
+    u times that sum; one wrong site (a bad index, a dropped term) gives a ratio of order 1.
+    """
+    n = np.linalg.norm(src, axis=-1)
+    s = np.zeros_like(n)
+    for ax in range(4):
+        s += np.roll(n, 1, axis=ax) + np.roll(n, -1, axis=ax)
+    err = np.linalg.norm(got - want, axis=-1)
+    x, y, z, t = np.meshgrid(*[np.arange(v) for v in dims[::-1]], indexing="ij")[::-1]
+    mask = ((x + y + z + t) % 2) == out_parity
+    return float((err[mask] / s[mask]).max())
+
+
+# unit roundoff of the storage formats (binary16 for FP16 storage, binary32)
+U_F16 = 2.0 ** -11
+U_F32 = 2.0 ** -24

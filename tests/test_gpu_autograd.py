@@ -84,3 +84,49 @@ def test_gradcheck_solve_and_action(ctx):
 
     assert torch.autograd.gradcheck(f_solve, (Ut, bt), eps=1e-6, atol=1e-6, rtol=1e-5, fast_mode=True)
     assert torch.autograd.gradcheck(f_action, (Ut, bt), eps=1e-6, atol=1e-5, rtol=1e-5, fast_mode=True)
+
+
+def test_autograd_functions_at_24x4_config(ctx):
+    """The differentiation workload through both torch.autograd Functions: 24^4, smooth links
+    eps = 0.3 (seed 1004), m = 0.05, phi from seed 2004 (and w from seed 2005 for the solve).
+
+    StaggeredAction: S, grad_phi = 2 chi and the projected su(3) force.  StaggeredSolve with
+    L = Re(w^dag x): x, grad_b = M^-1 w and the Euclidean link gradient.  The oracle's own CG
+    (tol 1e-12) gives chi, x and lambda; the GPU's solves (tol 1e-12) may differ from them by
+    kappa * 1e-12 each (kappa <= (m^2 + 64) / m^2), and quantities bilinear in them by twice
+    that.  On the GPU's own vectors the gradients must equal the oracle's derivative formulas
+    to 1e-12."""
+    dims, mass, tol = (24, 24, 24, 24), 0.05, 1e-12
+    kappa = (mass ** 2 + 64) / mass ** 2
+    U = synth.gauge(dims, "smooth", seed=1004, eps=0.3)
+    phi = _even(dims, 2004)
+    w = _even(dims, 2005)
+
+    print("24^4 action", flush=True)
+    Ut = dev(U).requires_grad_(True)
+    pt = dev(phi).requires_grad_(True)
+    S = staggered_action(Ut, pt, mass, ctx, project=True, tol=tol)
+    S.backward()
+    chi_g = host(pt.grad) / 2.0      # grad_phi = 2 chi (the library scales by 2, exact)
+    F = host(Ut.grad)
+    chi_o, st, _, _ = oracle.cg(dims, U, mass, phi, tol=tol)
+    assert st == 0
+    assert rel(chi_g, chi_o) <= kappa * tol
+    S_o = np.vdot(phi, chi_o).real
+    assert abs(float(S) - S_o) <= 2 * kappa * tol * abs(S_o)
+    assert rel(F, oracle.force(dims, U, chi_g)) <= 1e-12
+    assert rel(F, oracle.force(dims, U, chi_o)) <= 2 * kappa * tol
+
+    print("24^4 solve", flush=True)
+    Ut2 = dev(U).requires_grad_(True)
+    bt = dev(phi).requires_grad_(True)
+    x = staggered_solve(Ut2, bt, mass, ctx, tol=tol)
+    L = (torch.conj(dev(w)) * x).sum().real
+    L.backward()
+    x_g, lam_g, G = host(x.detach()), host(bt.grad), host(Ut2.grad)
+    lam_o, st, _, _ = oracle.cg(dims, U, mass, w, tol=tol)
+    assert st == 0
+    assert rel(x_g, chi_o) <= kappa * tol
+    assert rel(lam_g, lam_o) <= kappa * tol
+    assert rel(G, oracle.force(dims, U, x_g, lam_g, mode=1)) <= 1e-12
+    assert rel(G, oracle.force(dims, U, chi_o, lam_o, mode=1)) <= 2 * kappa * tol

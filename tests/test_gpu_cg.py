@@ -53,8 +53,12 @@ def test_cg_fp64_config_32x8_smooth(ctx):
     b = synth.source(dims, 0, seed=2001)
     x, st = _solve(ctx, dims, U, mass, b)
     assert st[0]["status"] == 0
-    assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+    tr = oracle.true_residual(dims, U, mass, b, x)
+    assert tr <= 1e-10 and abs(tr - st[0]["true_rel_residual"]) <= 1e-3 * tr + 1e-16
     assert np.abs(x * (np.indices(x.shape[:4]).sum(0) % 2 == 1)[..., None]).max() == 0.0
+    xo, so, _, _ = oracle.cg(dims, U, mass, b)
+    assert so == 0
+    assert rel(x, xo) <= (mass ** 2 + 64) / mass ** 2 * 1e-10
 
 
 @pytest.mark.parametrize("prec,recon", [(lqs.F32, 18), (lqs.F16, 18), (lqs.F32, 12), (lqs.F16, 12)])

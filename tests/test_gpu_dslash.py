@@ -3,15 +3,17 @@
 Sizes span several 256-thread blocks and ragged tails (4x6x8x10 has Vh = 960,
 not a multiple of 256); 32^3x8 and 64^3x16 are the benchmark lattices, run in
 the launch configuration the benchmark uses.
-FP64 bar: relative L2 error <= 1e-12.  FP32 / FP16-storage bars: see
-test_hop_low_precision.
+FP64 bar: relative L2 error <= 1e-12.  FP32 / FP16-storage bars: a relative L2
+error of a few unit roundoffs, and at every output site an error of at most
+SITE_C unit roundoffs times the summed norms of its eight input neighbours
+(see test_hop_low_precision and gpu_util.site_error_ratio).
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import dev, field, gauge, host, lex_of, rel
+from gpu_util import U_F16, U_F32, dev, field, gauge, host, lex_of, rel, site_error_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +25,16 @@ def ctx():
     c = lqs.Context(0)
     yield c
     c.close()
+
+
+# Per-site bound in unit roundoffs.  Per neighbour term: the rounded link
+# changes U v by at most |dU|_F |v| <= sqrt(18) u |v| (the rebuilt third row of
+# a 12-real link adds about 2 u per entry), the rounded vector (six components
+# scaled by the site's largest) by sqrt(6) u |v|; the output rounding adds
+# sqrt(6) u times the largest output component.  In the worst alignment that
+# is under 10 u per unit of summed neighbour norm; FP32 accumulation adds
+# about 11 u_f32.  16 leaves a margin; one wrong site gives a ratio near 1.
+SITE_C = 16
 
 
 def _case(dims, kind, seed):
@@ -76,6 +88,9 @@ def test_hop_low_precision(ctx, prec, recon, bound):
     want = oracle.dslash(dims, U, src, 0)
     err = rel(got, want)
     assert err <= bound, err
+    u = U_F16 if prec == lqs.F16 else U_F32
+    ratio = site_error_ratio(dims, got, want, src, 0)
+    assert ratio <= SITE_C * u, (ratio / u)
 
 
 @pytest.mark.parametrize("prec", [lqs.F64, lqs.F32, lqs.F16])
@@ -140,15 +155,22 @@ def test_full_size_hop_64x16(ctx):
 
 
 def test_full_size_low_precision_hops_64x16(ctx):
-    """64^3 x 16: the FP16 12-real hop the timed solve runs, and FP32 12-real, against the oracle."""
+    """64^3 x 16: the FP16 12-real hop the timed solve runs, and FP32 12-real, against the oracle,
+    in the launch configuration of the timed solve (default shape, streaming link loads); every
+    output site is held to the per-site rounding bound, not only the global norm."""
     dims = (64, 64, 64, 16)
     U = synth.gauge(dims, "smooth", seed=1002, eps=0.3)
     src = synth.source(dims, 1, seed=2002)
-    g = gauge(ctx, dims, U, lqs.fmt(lqs.F16, 12) | lqs.fmt(lqs.F32, 12))
+    g = gauge(ctx, dims, U, lqs.fmt(lqs.F16, 12) | lqs.fmt(lqs.F32, 12) | lqs.fmt(lqs.F16, 18))
     want = oracle.dslash(dims, U, src, 0)
-    for prec, bound in ((lqs.F16, 4e-3), (lqs.F32, 2e-6)):
-        got = lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, src, 1, prec), recon=12))
+    for prec, recon, bound, u in ((lqs.F16, 12, 4e-3, U_F16), (lqs.F32, 12, 2e-6, U_F32),
+                                  (lqs.F16, 18, 4e-3, U_F16)):
+        print(f"64^3x16 hop prec={prec} recon={recon}", flush=True)
+        got = lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, src, 1, prec), recon=recon))
         assert rel(got, want) <= bound
+        ratio = site_error_ratio(dims, got, want, src, 0)
+        assert ratio <= SITE_C * u, (prec, recon, ratio / u)
+        del got
 
 
 def test_full_size_sixteen_rhs_hop_64x16(ctx):
@@ -167,4 +189,7 @@ def test_full_size_sixteen_rhs_hop_64x16(ctx):
             assert np.array_equal(ym[k], ys), k
         for k, w in want.items():
             assert rel(ym[k], w) <= bound, (prec, k)
+            if prec == lqs.F32:
+                ratio = site_error_ratio(dims, ym[k], w, srcs[k], 0)
+                assert ratio <= SITE_C * U_F32, (k, ratio / U_F32)
         del ym
