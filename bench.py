@@ -580,15 +580,26 @@ def run_suite(a):
                                                       persistent=True)), 3)
             ctx.set_tuning(False)
             # one call, multi-kernel: the lattices run concurrently on side streams
-            ts = timed(lambda: lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs], tol=TOL,
-                                            inner_prec=pr, reliable_interval=100), 3)
+            # HIP events on the stream of the cooperative launch (cg_solve returns after it)
+            ev_ms = event_ms(lambda: st.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
+                                                            tol=TOL, inner_prec=pr, reliable_interval=100,
+                                                            persistent=True)), 3)
+            pst = st[-1]
+            stc = []
+            ts = timed(lambda: stc.append(lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_()) for g_, m_, b_, x_ in probs],
+                                                       tol=TOL, inner_prec=pr, reliable_interval=100)), 3)
 
             def sequential():
                 for g_, m_, b_, x_ in probs:
                     lqs.cg_solve(ctx, [(g_, m_, b_, x_.zero_())], tol=TOL, inner_prec=pr, reliable_interval=100)
             tq = timed(sequential, 3)
             emit({"suite": "uneven_batch", "lattices": [s_[0] for s_ in specs], "masses": [s_[1] for s_ in specs],
-                  "inner": prec, "persistent_tuned": tuned, "persistent_s": round(tp, 5),
+                  "inner": prec, "persistent_tuned": tuned, "persistent_event_ms": round(ev_ms, 4),
+                  "persistent_group_ms": [round(1e3 * r["device_seconds"], 4) for r in pst],
+                  "persistent_us_per_iter": [round(1e6 * r["device_seconds"] / max(r["iters"], 1), 2) for r in pst],
+                  "concurrent_us_per_iter": [round(1e6 * r["device_seconds"] / max(r["iters"], 1), 2)
+                                             for r in stc[-1]],
+                  "persistent_s": round(tp, 5),
                   "concurrent_multikernel_s": round(ts, 5), "sequential_s": round(tq, 5),
                   "persistent_vs_sequential": round(tq / tp, 2), "concurrent_vs_sequential": round(tq / ts, 2),
                   "iters": [r["iters"] for r in st[-1]],

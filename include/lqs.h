@@ -218,6 +218,10 @@ typedef struct {
     int32_t restarts;          /* FP64 CG: restarts after a failed true-residual check      */
     double true_rel_residual;  /* ||b - M x|| / ||b|| in FP64 at return                     */
     double seconds;            /* wall time of the whole call                               */
+    double device_seconds;     /* GPU time of this problem's solve: persistent = 1, its block
+                                  group's start to end (device wall clock); cg_solve otherwise,
+                                  from the first to the last kernel of the problem (stream
+                                  events); 0 where not measured (cg_solve_multishift)         */
 } lqs_cg_stats;
 
 /* Solve nprob systems.  stats receives one entry per (problem, right-hand

@@ -650,6 +650,7 @@ struct CgRun {
     size_t sbytes = 0;
     CgState *hs[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t tev[2] = {nullptr, nullptr};  // timing: first and last kernel of the solve
     int inflight = 0, slot = 0;
     int64_t enqueued = 0, cap = 0;
     bool done = false;
@@ -667,6 +668,8 @@ struct CgRun {
     ~CgRun()
     {
         for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : tev)
             if (e) (void)hipEventDestroy(e);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -729,6 +732,9 @@ struct CgRun {
             S.phase = CG_RUNNING;
             hs[0][r] = S;
         }
+        LQS_HIP(hipEventCreate(&tev[0]));
+        LQS_HIP(hipEventCreate(&tev[1]));
+        LQS_HIP(hipEventRecord(tev[0], s));
         LQS_HIP(hipMemcpyAsync(v.state, hs[0], sbytes, hipMemcpyHostToDevice, s));
         cg_init(ctx, gauge(), v, prm.use_x0 != 0, s);
         LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -793,6 +799,10 @@ struct CgRun {
             LQS_HIP(hipMemcpyAsync(hs[0], v.state, sbytes, hipMemcpyDeviceToHost, s));
             LQS_HIP(hipStreamSynchronize(s));
         }
+        float dev_ms = 0.f;
+        LQS_HIP(hipEventRecord(tev[1], s));
+        LQS_HIP(hipEventSynchronize(tev[1]));
+        LQS_HIP(hipEventElapsedTime(&dev_ms, tev[0], tev[1]));
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         for (int r = 0; r < nrhs; ++r) {
             const CgState &S = hs[0][r];
@@ -802,6 +812,7 @@ struct CgRun {
             o.restarts = S.restarts;
             o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
             o.seconds = secs;
+            o.device_seconds = 1e-3 * dev_ms;
             switch (S.phase) {
             case CG_CONVERGED: o.status = LQS_OK; break;
             case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;

@@ -354,7 +354,10 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
         if (hs.phase == CG_NONFINITE) stats[i].status = LQS_ENONFINITE;
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int i = 0; i < nmass; ++i) stats[i].seconds = secs;
+    for (int i = 0; i < nmass; ++i) {
+        stats[i].seconds = secs;
+        stats[i].device_seconds = 0.0;
+    }
 }
 
 }  // namespace lqs

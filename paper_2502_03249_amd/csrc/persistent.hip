@@ -134,7 +134,8 @@ __device__ void p_fin_residual(CgState &S, double r2)
 
 template <int P, int R, int PA, int BS>
 __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int nlat, CgState *st_out, GroupBar *bars,
-                                                           uint32_t *abort_flag, int max_trips)
+                                                           uint32_t *abort_flag, int max_trips,
+                                                           unsigned long long *clk)
 {
     typedef typename RealOf<P>::type T;
     typedef typename RealOf<PA>::type TA;
@@ -151,6 +152,8 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
     __syncthreads();
     GroupBar *gb = bars + lat;
     const int nb = L.nblocks, lb = blockIdx.x - L.block0;
+    // the group's device time: its first block's start and end (device wall clock)
+    if (lb == 0 && threadIdx.x == 0) clk[2 * lat] = wall_clock64();
     uint32_t gen = 0;
     const int vh = L.g.vh;
 
@@ -360,7 +363,10 @@ __global__ void __launch_bounds__(BS) persistent_cg_kernel(const PLat *lats, int
         if (fp64_residual(false, r2) && threadIdx.x == 0) S.true_r2 = r2;
         __syncthreads();
     }
-    if (lb == 0 && threadIdx.x == 0) st_out[lat] = S;
+    if (lb == 0 && threadIdx.x == 0) {
+        st_out[lat] = S;
+        clk[2 * lat + 1] = wall_clock64();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -452,6 +458,10 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
     const size_t bar_bytes = sizeof(GroupBar) * PMAX_LAT + 16;
     GroupBar *bars = (GroupBar *)ctx.workspace("pcg.bar", bar_bytes);
     uint32_t *abort_flag = (uint32_t *)(bars + PMAX_LAT);
+    unsigned long long *clk = (unsigned long long *)ctx.workspace("pcg.clk", 2 * sizeof(unsigned long long) * nlat);
+    std::vector<unsigned long long> hclk(2 * nlat);
+    int clk_khz = 0;
+    LQS_HIP(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx.device));
     std::vector<CgState> init(nlat), hs(nlat);
     const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
     const double delta =
@@ -498,11 +508,21 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
         LQS_HIP(hipMemsetAsync(bars, 0, bar_bytes, s));
         int n = nlat;
         int trips = max_trips;
-        void *args[] = {(void *)&dL, (void *)&n, (void *)&dS, (void *)&bars, (void *)&abort_flag, (void *)&trips};
+        void *args[] = {(void *)&dL, (void *)&n,    (void *)&dS,   (void *)&bars,
+                        (void *)&abort_flag, (void *)&trips, (void *)&clk};
         LQS_HIP(hipLaunchCooperativeKernel(fn, dim3(b0), dim3(bs), args, 0, s));
-        LQS_HIP(hipMemcpyAsync(hs.data(), dS, sizeof(CgState) * nlat, hipMemcpyDeviceToHost, s));
-        LQS_HIP(hipMemcpyAsync(&habort, abort_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        LQS_HIP(hipStreamSynchronize(s));
+        // From here the kernel and the copies into host memory may be in flight:
+        // on any error the stream is drained before the host buffers go away.
+        try {
+            LQS_HIP(hipMemcpyAsync(hs.data(), dS, sizeof(CgState) * nlat, hipMemcpyDeviceToHost, s));
+            LQS_HIP(hipMemcpyAsync(&habort, abort_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            LQS_HIP(hipMemcpyAsync(hclk.data(), clk, 2 * sizeof(unsigned long long) * nlat, hipMemcpyDeviceToHost,
+                                   s));
+            LQS_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            throw;
+        }
         LQS_REQUIRE(habort == 0, LQS_EHIP, "persistent solve: group barrier timed out");
     };
 
@@ -543,6 +563,7 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
         o.restarts = S.restarts;
         o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
         o.seconds = secs;
+        o.device_seconds = clk_khz > 0 ? (double)(hclk[2 * l + 1] - hclk[2 * l]) / (1e3 * clk_khz) : 0.0;
         switch (S.phase) {
         case CG_CONVERGED: o.status = LQS_OK; break;
         case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;
