@@ -221,7 +221,8 @@ typedef struct {
     double device_seconds;     /* GPU time of this problem's solve: persistent = 1, its block
                                   group's start to end (device wall clock); cg_solve otherwise,
                                   from the first to the last kernel of the problem (stream
-                                  events); 0 where not measured (cg_solve_multishift)         */
+                                  events); 0 where not measured (cg_solve_noalloc,
+                                  cg_solve_multishift)                                      */
 } lqs_cg_stats;
 
 /* Solve nprob systems.  stats receives one entry per (problem, right-hand
@@ -235,6 +236,27 @@ typedef struct {
  * single block. */
 lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const lqs_cg_params *params,
                     lqs_cg_stats *stats, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cg_solve of
+ * ONE problem (nrhs 1..16, persistent = 0) whose workspace is a fixed device
+ * array of LQS_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU,
+ * held until the process ends (its address is taken once per device when a
+ * context is created).  The call performs no device or pinned-host allocation
+ * and creates no events, streams or graphs: it launches the same kernels with
+ * the same launch shapes as cg_solve, eagerly on `stream`, and waits for a
+ * state poll every eight iterations; the results equal cg_solve's.  The
+ * caller still passes b, x and the gauge (created beforehand).  A problem
+ * whose workspace (three inner-precision fields, the residual, in mixed
+ * precision the inner solution and an FP64 field, plus reduction partials:
+ * about 200 bytes per even site and right-hand side in FP64, 150 with FP16
+ * inner) exceeds the array returns LQS_EINVAL before anything is launched.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (the solve initialises all it reads): calls that
+ * overlap on one GPU, from several threads or streams, race.  Hop profiling
+ * (lqs_profile_hops) and autotuning are not applied inside this call. */
+#define LQS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+lqs_status cg_solve_noalloc(lqs_ctx *ctx, const lqs_problem *prob, const lqs_cg_params *params,
+                            lqs_cg_stats *stats, void *stream);
 
 /* Several masses on one Krylov space: x_i = (m_i^2 - D_eo D_oe)^-1 b for
  * i < nmass (multi-shift CG; the systems differ by the shifts m_i^2 - m_0^2

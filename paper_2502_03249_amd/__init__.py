@@ -89,7 +89,8 @@ EXPORTS = ["lqs_ctx_create", "lqs_ctx_destroy", "lqs_set_tuning", "lqs_gauge_cre
            "lqs_field_bytes", "lqs_field_pack", "lqs_field_unpack", "dslash_apply", "dslash_dagger", "cg_solve",
            "fermion_force", "lqs_strerror", "lqs_last_error", "lqs_profile_hops", "lqs_profile_hops_result",
            "lqs_field_dot", "cg_solve_multishift", "lqs_gauge_fix_temporal", "gauge_action", "gauge_force",
-           "link_update", "kinetic_energy", "hmc_trajectory", "lqs_set_graphs", "lqs_field_unpack_scaled"]
+           "link_update", "kinetic_energy", "hmc_trajectory", "lqs_set_graphs", "lqs_field_unpack_scaled",
+           "cg_solve_noalloc"]
 
 
 def lib():
@@ -119,6 +120,8 @@ def lib():
     L.dslash_dagger.argtypes = [vp, vp, i32, ctypes.POINTER(LqsField), ctypes.POINTER(LqsField), vp]
     L.cg_solve.argtypes = [vp, i32, ctypes.POINTER(LqsProblem), ctypes.POINTER(LqsCgParams),
                            ctypes.POINTER(LqsCgStats), vp]
+    L.cg_solve_noalloc.argtypes = [vp, ctypes.POINTER(LqsProblem), ctypes.POINTER(LqsCgParams),
+                                   ctypes.POINTER(LqsCgStats), vp]
     L.fermion_force.argtypes = [vp, vp, vp, vp, d, i32, vp, vp]
     L.cg_solve_multishift.argtypes = [vp, vp, i32, ctypes.POINTER(d), vp, ctypes.POINTER(vp),
                                       ctypes.POINTER(LqsCgParams), ctypes.POINTER(LqsCgStats), vp]
@@ -334,6 +337,22 @@ def cg_solve(ctx, problems, tol=1e-10, max_iter=10000, inner_prec=F64, inner_rec
                       float(reliable_delta), 1 if use_x0 else 0, 1 if persistent else 0)
     stats = (LqsCgStats * total)()
     st = lib().cg_solve(ctx.handle, n, arr, ctypes.byref(prm), stats, _stream(stream))
+    if st < 0 and st not in (EBREAKDOWN, ENONFINITE):
+        _check(st)
+    return [s.as_dict() for s in stats]
+
+
+def cg_solve_noalloc(ctx, problem, tol=1e-10, max_iter=10000, inner_prec=F64, inner_recon=18, reliable_interval=0,
+                     reliable_delta=0.0, use_x0=False, stream=None):
+    """cg_solve of one (gauge, mass, b, x) problem with the library's fixed scratch array as workspace (no device
+    allocation inside the call); returns per-rhs stats dicts."""
+    g, m, b, x = problem
+    assert b.prec == F64 and x.prec == F64 and b.parity == 0 and x.parity == 0 and b.nrhs == x.nrhs
+    pb = LqsProblem(g.handle, float(m), b.nrhs, ctypes.c_void_p(b.data.data_ptr()), ctypes.c_void_p(x.data.data_ptr()))
+    prm = LqsCgParams(float(tol), int(max_iter), PREC[inner_prec], int(inner_recon), int(reliable_interval),
+                      float(reliable_delta), 1 if use_x0 else 0, 0)
+    stats = (LqsCgStats * b.nrhs)()
+    st = lib().cg_solve_noalloc(ctx.handle, ctypes.byref(pb), ctypes.byref(prm), stats, _stream(stream))
     if st < 0 and st not in (EBREAKDOWN, ENONFINITE):
         _check(st)
     return [s.as_dict() for s in stats]

@@ -179,7 +179,13 @@ lqs_status lqs_ctx_create(int32_t device, const char *tune_cache_path, lqs_ctx *
             LQS_HIP(e);
         }
         c->num_cu = c->prop.multiProcessorCount;
-        c->tuner.reset(new Tuner(tune_cache_path));
+        try {
+            c->noalloc_scratch = noalloc_scratch(device);
+            c->tuner.reset(new Tuner(tune_cache_path));
+        } catch (...) {
+            delete c;
+            throw;
+        }
         *out = c;
     });
 }
@@ -354,6 +360,39 @@ lqs_status dslash_dagger(lqs_ctx *ctx, const lqs_gauge *g, int32_t recon, const 
     return dslash_common(ctx, g, recon, in, out, stream, 1);
 }
 
+static void check_cg_params(const lqs_cg_params &p)
+{
+    LQS_REQUIRE(p.tol > 0 && std::isfinite(p.tol), LQS_EINVAL, "tol must be positive");
+    LQS_REQUIRE(p.max_iter >= 1, LQS_EINVAL, "max_iter must be >= 1");
+    LQS_REQUIRE(p.inner_prec >= 0 && p.inner_prec <= 2, LQS_EINVAL, "bad inner precision");
+    LQS_REQUIRE(p.inner_recon == 18 || p.inner_recon == 12, LQS_EINVAL, "inner_recon must be 18 or 12");
+    LQS_REQUIRE(p.reliable_interval >= 0 && p.reliable_delta >= 0 && p.reliable_delta < 1, LQS_EINVAL,
+                "bad reliable-update parameters");
+}
+
+static void check_problem(const lqs_problem &pb, const lqs_cg_params &p)
+{
+    LQS_REQUIRE(pb.gauge != nullptr, LQS_EINVAL, "problem without gauge");
+    LQS_REQUIRE(pb.nrhs >= 1 && pb.nrhs <= 16, LQS_EINVAL, "nrhs must be in 1..16");
+    LQS_REQUIRE(std::isfinite(pb.mass) && pb.mass >= 0, LQS_EINVAL, "mass must be finite and >= 0");
+    check_ptr(pb.b, "b");
+    check_ptr(pb.x, "x");
+    (void)pb.gauge->ref(p.inner_prec, p.inner_recon);
+    if (p.persistent) LQS_REQUIRE(pb.nrhs == 1, LQS_EUNSUPPORTED, "persistent solve needs nrhs == 1");
+}
+
+// The worst per-right-hand-side status: errors before warnings before OK.
+static lqs_status worst_status(const lqs_cg_stats *stats, int n)
+{
+    lqs_status worst = LQS_OK;
+    for (int i = 0; i < n; ++i) {
+        const lqs_status si = stats[i].status;
+        if (si < 0 && (worst >= 0 || si < worst)) worst = si;
+        else if (worst == LQS_OK && si > 0) worst = si;
+    }
+    return worst;
+}
+
 lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const lqs_cg_params *params,
                     lqs_cg_stats *stats, void *stream)
 {
@@ -363,25 +402,8 @@ lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const
         LQS_REQUIRE(nprob >= 1 && probs != nullptr, LQS_EINVAL, "need at least one problem");
         LQS_REQUIRE(params != nullptr && stats != nullptr, LQS_EINVAL, "params or stats is NULL");
         const lqs_cg_params &p = *params;
-        LQS_REQUIRE(p.tol > 0 && std::isfinite(p.tol), LQS_EINVAL, "tol must be positive");
-        LQS_REQUIRE(p.max_iter >= 1, LQS_EINVAL, "max_iter must be >= 1");
-        LQS_REQUIRE(p.inner_prec >= 0 && p.inner_prec <= 2, LQS_EINVAL, "bad inner precision");
-        LQS_REQUIRE(p.inner_recon == 18 || p.inner_recon == 12, LQS_EINVAL, "inner_recon must be 18 or 12");
-        LQS_REQUIRE(p.reliable_interval >= 0 && p.reliable_delta >= 0 && p.reliable_delta < 1, LQS_EINVAL,
-                    "bad reliable-update parameters");
-        int total = 0;
-        for (int i = 0; i < nprob; ++i) {
-            const lqs_problem &pb = probs[i];
-            LQS_REQUIRE(pb.gauge != nullptr, LQS_EINVAL, "problem without gauge");
-            LQS_REQUIRE(pb.nrhs >= 1 && pb.nrhs <= 16, LQS_EINVAL, "nrhs must be in 1..16");
-            LQS_REQUIRE(std::isfinite(pb.mass) && pb.mass >= 0, LQS_EINVAL, "mass must be finite and >= 0");
-            check_ptr(pb.b, "b");
-            check_ptr(pb.x, "x");
-            (void)pb.gauge->ref(p.inner_prec, p.inner_recon);
-            if (p.persistent) LQS_REQUIRE(pb.nrhs == 1, LQS_EUNSUPPORTED, "persistent solve needs nrhs == 1");
-            total += pb.nrhs;
-        }
-        (void)total;
+        check_cg_params(p);
+        for (int i = 0; i < nprob; ++i) check_problem(probs[i], p);
         LQS_HIP(hipSetDevice(ctx->device));
         hipStream_t s = as_stream(stream);
         if (p.persistent) {
@@ -399,11 +421,24 @@ lqs_status cg_solve(lqs_ctx *ctx, int32_t nprob, const lqs_problem *probs, const
         }
         int n = 0;
         for (int i = 0; i < nprob; ++i) n += probs[i].nrhs;
-        for (int i = 0; i < n; ++i) {
-            const lqs_status si = stats[i].status;
-            if (si < 0 && (worst >= 0 || si < worst)) worst = si;
-            else if (worst == LQS_OK && si > 0) worst = si;
-        }
+        worst = worst_status(stats, n);
+    });
+    return st != LQS_OK ? st : worst;
+}
+
+lqs_status cg_solve_noalloc(lqs_ctx *ctx, const lqs_problem *prob, const lqs_cg_params *params,
+                            lqs_cg_stats *stats, void *stream)
+{
+    lqs_status worst = LQS_OK;
+    lqs_status st = guard([&] {
+        LQS_REQUIRE(ctx != nullptr && prob != nullptr, LQS_EINVAL, "ctx or problem is NULL");
+        LQS_REQUIRE(params != nullptr && stats != nullptr, LQS_EINVAL, "params or stats is NULL");
+        check_cg_params(*params);
+        check_problem(*prob, *params);
+        LQS_REQUIRE(!params->persistent, LQS_EUNSUPPORTED, "cg_solve_noalloc has no persistent mode");
+        LQS_HIP(hipSetDevice(ctx->device));
+        cg_solve_noalloc_impl(*ctx, *prob, *params, stats, as_stream(stream));
+        worst = worst_status(stats, prob->nrhs);
     });
     return st != LQS_OK ? st : worst;
 }

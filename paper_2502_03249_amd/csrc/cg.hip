@@ -20,6 +20,7 @@
 // paper cites, Clark et al. 2010).
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "hop.hpp"
 
@@ -632,6 +633,37 @@ static bool final_phase(int32_t ph)
     return ph == CG_CONVERGED || ph == CG_BREAKDOWN || ph == CG_NONFINITE || ph == CG_MAXITER;
 }
 
+// Initial state records of one problem's right-hand sides.
+static void cg_initial_states(const lqs_cg_params &prm, int nrhs, CgState *out)
+{
+    const bool mixed = prm.inner_prec != F64;
+    const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
+    const double delta =
+        mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : default_reliable_delta(prm.inner_prec)) : 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        CgState S{};
+        S.stop2 = prm.tol * prm.tol;
+        S.delta2 = delta * delta;
+        S.rel_interval = rel_interval;
+        S.max_iter = prm.max_iter;
+        S.phase = CG_RUNNING;
+        out[r] = S;
+    }
+}
+
+// Device workspace of one problem, every buffer starting on a 256-byte boundary.
+size_t cg_workspace_bytes(const Gauge &gauge, const lqs_cg_params &prm, int nrhs)
+{
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const bool mixed = prm.inner_prec != F64;
+    const size_t fp = field_bytes(gauge.g, prm.inner_prec, nrhs), fa = field_bytes(gauge.g, mixed ? F32 : F64, nrhs),
+                 f64 = field_bytes(gauge.g, F64, nrhs);
+    const size_t part = sizeof(double) * (size_t)cg_partials_needed(gauge, nrhs) * nrhs;
+    size_t n = up(sizeof(CgState) * nrhs) + 2 * up(part) + 3 * up(fp) + up(fa);
+    if (mixed) n += up(fa) + up(f64);
+    return n;
+}
+
 // One problem driven as a small state machine, so that several problems on
 // their own streams can be advanced in turn by one host thread.
 namespace {
@@ -683,6 +715,20 @@ struct CgRun {
     }
     const Gauge &gauge() const { return *pb.gauge; }
 
+    // Buffers come from the context's workspace, or, when `arena` is set,
+    // are carved from that preallocated device region (no allocation).
+    char *arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    CgState *arena_host = nullptr;  // host mirror (two records per rhs) with an arena
+    void *buf(const std::string &slot, size_t bytes)
+    {
+        if (!arena) return ctx.workspace(slot + tag, bytes);
+        const size_t off = (arena_used + 255) & ~size_t(255);
+        LQS_REQUIRE(off + bytes <= arena_bytes, LQS_EINVAL, "workspace exceeds the preallocated region");
+        arena_used = off + bytes;
+        return arena + off;
+    }
+
     void setup()
     {
         const Geom &g = gauge().g;
@@ -694,51 +740,54 @@ struct CgRun {
         v.nrhs = nrhs;
         v.mass = pb.mass;
         (void)gauge().ref(v.prec, v.recon);  // format must exist
+        v.max_blocks = cg_partials_needed(gauge(), nrhs);
+        sbytes = sizeof(CgState) * nrhs;
+        // every size is checked before the first launch
+        const size_t need = cg_workspace_bytes(gauge(), prm, nrhs);
+        LQS_REQUIRE(!arena || need <= arena_bytes, LQS_EINVAL,
+                    "solve needs " + std::to_string(need) + " bytes of workspace, the preallocated region holds " +
+                        std::to_string(arena_bytes));
         const int64_t fp = field_bytes(g, v.prec, nrhs), fa = field_bytes(g, v.acc_prec, nrhs),
                       f64 = field_bytes(g, F64, nrhs);
-        v.p = ctx.workspace("cg.p" + tag, fp);
-        v.q = ctx.workspace("cg.q" + tag, fp);
-        v.t = ctx.workspace("cg.t" + tag, fp);
+        v.state = (CgState *)buf("cg.state", sbytes);
+        v.partials = (double *)buf("cg.partials", sizeof(double) * (size_t)v.max_blocks * nrhs);
+        v.partials2 = (double *)buf("cg.partials2", sizeof(double) * (size_t)v.max_blocks * nrhs);
+        v.p = buf("cg.p", fp);
+        v.q = buf("cg.q", fp);
+        v.t = buf("cg.t", fp);
         v.x = pb.x;
         v.b = (double *)pb.b;
         if (mixed) {
-            v.r = ctx.workspace("cg.r" + tag, fa);
-            v.xlo = ctx.workspace("cg.xlo" + tag, fa);
-            v.t64 = ctx.workspace("cg.t64" + tag, f64);
+            v.r = buf("cg.r", fa);
+            v.xlo = buf("cg.xlo", fa);
+            v.t64 = buf("cg.t64", f64);
             v.rhi = nullptr;
         } else {
-            v.r = ctx.workspace("cg.r" + tag, f64);
+            v.r = buf("cg.r", f64);
             v.xlo = pb.x;
             v.t64 = v.t;
             v.rhi = (double *)v.r;
         }
-        v.max_blocks = cg_partials_needed(gauge(), nrhs);
-        v.partials = (double *)ctx.workspace("cg.partials" + tag, sizeof(double) * (size_t)v.max_blocks * nrhs);
-        v.partials2 = (double *)ctx.workspace("cg.partials2" + tag, sizeof(double) * (size_t)v.max_blocks * nrhs);
-        v.state = (CgState *)ctx.workspace("cg.state" + tag, sizeof(CgState) * nrhs);
-        sbytes = sizeof(CgState) * nrhs;
-        char *host = (char *)ctx.pinned("cg.host" + tag, 2 * sbytes);
-        hs[0] = (CgState *)host;
-        hs[1] = (CgState *)(host + sbytes);
-        const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
-        const double delta =
-            mixed ? (prm.reliable_delta > 0 ? prm.reliable_delta : default_reliable_delta(prm.inner_prec)) : 0.0;
-        for (int r = 0; r < nrhs; ++r) {
-            CgState S{};
-            S.stop2 = prm.tol * prm.tol;
-            S.delta2 = delta * delta;
-            S.rel_interval = rel_interval;
-            S.max_iter = prm.max_iter;
-            S.phase = CG_RUNNING;
-            hs[0][r] = S;
+        if (arena) {
+            hs[0] = arena_host;
+            hs[1] = arena_host + nrhs;
+        } else {
+            char *host = (char *)ctx.pinned("cg.host" + tag, 2 * sbytes);
+            hs[0] = (CgState *)host;
+            hs[1] = (CgState *)(host + sbytes);
         }
-        LQS_HIP(hipEventCreate(&tev[0]));
-        LQS_HIP(hipEventCreate(&tev[1]));
-        LQS_HIP(hipEventRecord(tev[0], s));
+        cg_initial_states(prm, nrhs, hs[0]);
+        if (!arena) {
+            LQS_HIP(hipEventCreate(&tev[0]));
+            LQS_HIP(hipEventCreate(&tev[1]));
+            LQS_HIP(hipEventRecord(tev[0], s));
+        }
         LQS_HIP(hipMemcpyAsync(v.state, hs[0], sbytes, hipMemcpyHostToDevice, s));
         cg_init(ctx, gauge(), v, prm.use_x0 != 0, s);
-        LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-        LQS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        if (!arena) {
+            LQS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+            LQS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        }
         cap = (int64_t)prm.max_iter + 16 * chunk + 64;
     }
 
@@ -768,9 +817,22 @@ struct CgRun {
         }
         enqueued += chunk * poll_every;
         LQS_HIP(hipMemcpyAsync(hs[slot], v.state, sbytes, hipMemcpyDeviceToHost, s));
+        if (arena) {
+            // no events: wait for this poll at once
+            LQS_HIP(hipStreamSynchronize(s));
+            decide(hs[slot]);
+            return;
+        }
         LQS_HIP(hipEventRecord(ev[slot], s));
         ++inflight;
         slot ^= 1;
+    }
+
+    void decide(const CgState *h)
+    {
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all &= final_phase(h[r].phase);
+        if (all || enqueued > cap) done = true;
     }
 
     // with two polls in flight, wait for the older one and decide
@@ -779,9 +841,7 @@ struct CgRun {
         if (inflight < 2) return;
         LQS_HIP(hipEventSynchronize(ev[slot]));
         --inflight;
-        bool all = true;
-        for (int r = 0; r < nrhs; ++r) all &= final_phase(hs[slot][r].phase);
-        if (all || enqueued > cap) done = true;
+        decide(hs[slot]);
     }
 
     void finish()
@@ -800,9 +860,11 @@ struct CgRun {
             LQS_HIP(hipStreamSynchronize(s));
         }
         float dev_ms = 0.f;
-        LQS_HIP(hipEventRecord(tev[1], s));
-        LQS_HIP(hipEventSynchronize(tev[1]));
-        LQS_HIP(hipEventElapsedTime(&dev_ms, tev[0], tev[1]));
+        if (tev[0]) {
+            LQS_HIP(hipEventRecord(tev[1], s));
+            LQS_HIP(hipEventSynchronize(tev[1]));
+            LQS_HIP(hipEventElapsedTime(&dev_ms, tev[0], tev[1]));
+        }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         for (int r = 0; r < nrhs; ++r) {
             const CgState &S = hs[0][r];
@@ -923,6 +985,65 @@ void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lq
         throw;
     }
     cleanup();
+}
+
+
+// ---------------------------------------------------------------------------
+// A solve that allocates nothing, for callers that cannot allocate device
+// memory.  Its workspace is a file-scope device array (each GPU the library
+// runs on holds its own copy until the process ends); host code never uses
+// the array's name as an address, only the per-device address fetched once
+// with hipGetSymbolAddress.  Every call on one GPU shares that GPU's array:
+// calls that overlap on one GPU race.  The solve runs eagerly on the caller's
+// stream (no graphs, no events, no pinned host buffers), with the kernels of
+// cg_solve and the same launch shapes.
+
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex scratch_mu;
+static void *scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of this GPU's scratch array; the device must be current.
+void *noalloc_scratch(int device)
+{
+    LQS_REQUIRE(device >= 0 && device < NOALLOC_MAX_DEVICES, LQS_EUNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *ptr = nullptr;
+        LQS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        scratch_ptr[device] = ptr;
+    }
+    return scratch_ptr[device];
+}
+
+void cg_solve_noalloc_impl(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats,
+                           hipStream_t s)
+{
+    LQS_REQUIRE(ctx.noalloc_scratch != nullptr, LQS_EHIP, "scratch address not set up");
+    const size_t need = cg_workspace_bytes(*pb.gauge, prm, pb.nrhs);
+    LQS_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, LQS_EINVAL,
+                "solve needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
+    // hop profiling records events it creates on demand: off for this call
+    struct ProfOff {
+        Ctx &c;
+        bool was;
+        ~ProfOff() { c.profiling = was; }
+    } prof{ctx, ctx.profiling};
+    ctx.profiling = false;
+    CgState host[2 * 16];
+    CgRun run(ctx, pb, prm, stats, s, "", std::chrono::steady_clock::now());
+    run.arena = (char *)ctx.noalloc_scratch;
+    run.arena_bytes = NOALLOC_SCRATCH_BYTES;
+    run.arena_host = host;
+    try {
+        run.setup();
+        while (!run.done) run.enqueue();
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        throw;
+    }
+    run.finish();
 }
 
 }  // namespace lqs

@@ -110,6 +110,7 @@ struct Ctx {
     int num_cu = 0;
     bool tuning = false;
     bool graphs = true;  // capture CG iteration rounds into HIP graphs
+    void *noalloc_scratch = nullptr;  // this device's scratch array (cg_solve_noalloc)
     std::unique_ptr<Tuner> tuner;
     // workspace buffers by slot, grown on demand, freed with the context
     std::map<std::string, std::pair<void *, size_t>> ws;
@@ -225,6 +226,14 @@ struct PersistentProblem {
 void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, const lqs_cg_params &prm,
                       lqs_cg_stats *stats, hipStream_t s);
 
+// cg.hip: device workspace of one problem's solve
+size_t cg_workspace_bytes(const Gauge &gauge, const lqs_cg_params &prm, int nrhs);
+// cg.hip: the allocation-free solve and its per-device scratch array
+constexpr size_t NOALLOC_SCRATCH_BYTES = LQS_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void *noalloc_scratch(int device);
+void cg_solve_noalloc_impl(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats,
+                           hipStream_t s);
 // cg.hip: one problem with the multi-kernel iteration (returns when done)
 void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
 // several problems, each on its own side stream, iterated concurrently
