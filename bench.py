@@ -53,26 +53,31 @@ def parse():
     ap.add_argument("--hop-reps", type=int, default=20)
     ap.add_argument("--only-hop", default=None, help="prec:recon, e.g. f64:18 -- hop launches only (profiling)")
     ap.add_argument("--only-copy", action="store_true", help="plain copy kernel only (counter calibration)")
+    ap.add_argument("--only-solve", action="store_true",
+                    help="one mixed-precision solve with the timed step's settings and nothing else (profiling)")
     ap.add_argument("--hop-nrhs", type=int, default=1, help="right-hand sides of the --only-hop launches")
     ap.add_argument("--no-temporal", action="store_true", help="skip the temporal-gauge solves")
     ap.add_argument("--dims", default=None, help="override lattice, e.g. 32,32,32,8")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads (size sweep, multi-RHS, batches, force); one JSON line each")
+    ap.add_argument("--suite-dims", default=None,
+                    help="lattices of the hop and CG size sweeps, e.g. '48,48,48,48;64,64,64,64'")
     ap.add_argument("--suite-only", default=None,
                     help="comma-separated suite sections: hop_sweep, cg_sweep, nmulti, temporal, multishift, "
                          "block_cg, uneven, small_cg, reliable, force, oracle, hmc")
     return ap.parse_args()
 
 
-# Sources that define the hop kernel's code: counter readings taken on other
-# sources are not reported.
+# Sources that define a kernel's code (the standalone hop unless an entry of the
+# counter summary names others): counter readings taken on other sources are
+# not reported.
 HOP_SOURCES = ["dev.hpp", "hop.hpp", "dslash.hip"]
 
 
-def src_hash():
+def src_hash(sources=None):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2502_03249_amd", "csrc")
-    for name in HOP_SOURCES:
+    for name in sources or HOP_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -86,7 +91,7 @@ def traffic_for(kernel_key, launches_sites):
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel_key)
-    if not e or e.get("src_hash") != src_hash():
+    if not e or e.get("src_hash") != src_hash(e.get("sources")):
         return None
     return e["bytes_per_launch"]
 
@@ -172,6 +177,13 @@ def main():
         return
 
     inner = lqs.PREC[a.inner]
+
+    if a.only_solve:
+        st = lqs.cg_solve(ctx, [(g, MASS, bf, xf)], tol=TOL, max_iter=20000, inner_prec=inner,
+                          inner_recon=a.recon, reliable_interval=a.reliable)
+        torch.cuda.synchronize()
+        print(json.dumps(st[0]))
+        return
 
     def solve(prec, recon, reliable):
         xf.zero_()
@@ -419,54 +431,100 @@ def run_suite(a):
         torch.cuda.synchronize()
         return U, g, b
 
-    # 1. hop size sweep (the hop at every format, standalone, stream events)
+    sweep_dims = [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 8), (24, 24, 24, 24),
+                  (32, 32, 32, 32), (48, 48, 48, 12), (64, 64, 64, 16), (48, 48, 48, 48), (64, 64, 64, 64)]
+    if a.suite_dims:
+        sweep_dims = [tuple(int(v) for v in d.split(",")) for d in a.suite_dims.split(";")]
+
+    def temporal_gauge(dims, U):
+        """The same links fixed to temporal gauge (U_t = 1 off the last slice), the paper's storage."""
+        Ud = torch.from_numpy(U).to(dev)
+        Uf, G = lqs.gauge_fix_temporal(ctx, dims, Ud)
+        del Ud
+        gt = lqs.Gauge(ctx, dims, Uf, lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+        del Uf
+        return gt, G
+
+    # 1. hop size sweep (Fig. 3 analogue): the hop at every format, standalone, stream events;
+    #    then the paper's storage (temporal gauge, 12 reals: 6 + 2/Nt links read per site)
     if want("hop_sweep"):
-        for dims in [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 8), (24, 24, 24, 24),
-                     (32, 32, 32, 32), (48, 48, 48, 12), (64, 64, 64, 16)]:
+        for dims in sweep_dims:
             U, g, _ = setup(dims, "smooth", 1002, [7])
             vh = int(np.prod(dims)) // 2
-            for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f16", 18), ("f16", 12)]:
+            src = torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev)
+
+            def one(gauge_, prec, recon, lps, storage):
                 pr = lqs.PREC[prec]
-                x = lqs.Field.from_lex(ctx, torch.from_numpy(synth.source(dims, 1, seed=7)).to(dev), 1, pr)
+                x = lqs.Field.from_lex(ctx, src, 1, pr)
                 y = x.like(parity=0)
-                ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 20)
-                mb = model.hop_model_bytes(pr, recon)
-                emit({"suite": "hop_size_sweep", "dims": dims, "prec": prec, "recon": recon, "us": round(1e3 * ms, 2),
-                      "model_GBps": round(mb * vh / ms / 1e6, 1), "GFLOPs": round(570 * vh / ms / 1e6, 1),
-                      "note": "lattice links fit in the 256 MB MALL" if mb * vh < 2.5e8 else "HBM"})
+                ms = event_ms(lambda: lqs.dslash_apply(ctx, gauge_, x, y, recon=recon), 20)
+                mb = model.hop_model_bytes(pr, recon, 1, lps)
+                nb = model.hop_min_bytes(pr, recon, 1, lps)
+                emit({"suite": "hop_size_sweep", "dims": dims, "storage": storage, "prec": prec, "recon": recon,
+                      "us": round(1e3 * ms, 2), "GFLOPs": round(570 * vh / ms / 1e6, 1),
+                      "model_GBps": round(mb * vh / ms / 1e6, 1), "alg_GBps": round(nb * vh / ms / 1e6, 1),
+                      "alg_frac_8TBps": round(nb * vh / ms / 1e6 / PEAK_HBM_GBPS, 3),
+                      "note": "links fit in the 256 MB MALL" if 8 * model.link_bytes(pr, recon) * vh < 2.5e8 else "HBM"})
+
+            for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)]:
+                one(g, prec, recon, 8, "ungauged")
             g.close()
+            gt, G = temporal_gauge(dims, U)
+            del G, U
+            for prec in ("f64", "f32", "f16"):
+                one(gt, prec, 12, 6 + 2 / dims[3], "temporal_gauge")
+            gt.close()
+            torch.cuda.empty_cache()
 
     # 1b. CG size sweep (the CG curve of Fig. 3): time per iteration and algorithmic GB/s of the
+    #     FP64 solver and the FP16-mixed solver, 8^4 .. 64^4, m 0.05; from 32^4 on also in the
+    #     paper's storage (temporal gauge, 12-real links), the source transformed with the gauge
     if want("cg_sweep"):
-        #     FP64 solver and the FP16-mixed solver, 8^4 .. 64^3x16, m 0.05
-        for dims in [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 24), (32, 32, 32, 32), (48, 48, 48, 12),
-                     (64, 64, 64, 16)]:
+        for dims in [d for d in sweep_dims if int(np.prod(d)) >= 8 ** 4]:
             U, g, b = setup(dims, "smooth", 1002, [2002])
             vh = int(np.prod(dims)) // 2
             x = b.like()
-            for inner, recon in (("f64", 18), ("f16", 12)):
+
+            def sweep(gauge_, bb, xx, inner, recon, storage, lps):
                 pr = lqs.PREC[inner]
-                lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr, inner_recon=recon,
+                lqs.cg_solve(ctx, [(gauge_, 0.05, bb, xx.zero_())], tol=TOL, inner_prec=pr, inner_recon=recon,
                              reliable_interval=100)
                 st = []
-                t = timed(lambda: st.append(lqs.cg_solve(ctx, [(g, 0.05, b, x.zero_())], tol=TOL, inner_prec=pr,
+                t = timed(lambda: st.append(lqs.cg_solve(ctx, [(gauge_, 0.05, bb, xx.zero_())], tol=TOL, inner_prec=pr,
                                                          inner_recon=recon, reliable_interval=100)), 2)
                 it = st[-1][0]["iters"]
-                by = model.cg_iteration_bytes(pr, lqs.F64 if pr == lqs.F64 else lqs.F32, recon) * vh
-                emit({"suite": "cg_size_sweep", "dims": dims, "inner": inner, "recon": recon, "s": round(t, 5),
-                      "iters": it, "us_per_iter": round(1e6 * t / it, 2), "alg_GBps": round(by * it / t / 1e9, 1),
-                      "true_res": st[-1][0]["true_rel_residual"]})
-            g.close()
+                by = model.cg_iteration_bytes(pr, lqs.F64 if pr == lqs.F64 else lqs.F32, recon, lps) * vh
+                emit({"suite": "cg_size_sweep", "dims": dims, "storage": storage, "inner": inner, "recon": recon,
+                      "s": round(t, 5), "iters": it, "us_per_iter": round(1e6 * t / it, 2),
+                      "device_us_per_iter": round(1e6 * st[-1][0]["device_seconds"] / it, 2),
+                      "alg_GBps": round(by * it / t / 1e9, 1), "true_res": st[-1][0]["true_rel_residual"],
+                      "converged": st[-1][0]["status"] == 0})
 
-    # 2. multi-vector hop: 32^4 (the paper's Table 2 lattice) and 32^3x8 with 16 sources
+            for inner, recon in (("f64", 18), ("f16", 12)):
+                sweep(g, b, x, inner, recon, "ungauged", 8)
+            g.close()
+            if int(np.prod(dims)) >= 32 ** 4:
+                gt, G = temporal_gauge(dims, U)
+                bsrc = torch.from_numpy(synth.source(dims, 0, seed=2002)).to(dev)
+                bt = lqs.Field.from_lex(ctx, (G * bsrc.unsqueeze(-2)).sum(-1), 0)
+                del G, bsrc
+                xt = bt.like()
+                for inner in ("f64", "f16"):
+                    sweep(gt, bt, xt, inner, 12, "temporal_gauge", 6 + 2 / dims[3])
+                gt.close()
+            del U
+            torch.cuda.empty_cache()
+
+    # 2. multi-vector hop: 32^4 (the paper's Table 2 lattice), 32^3x8 and 64^3x16 with 16 sources
     if want("nmulti"):
-        for dims in [(32, 32, 32, 32), (32, 32, 32, 8)]:
+        for dims in [(32, 32, 32, 32), (32, 32, 32, 8), (64, 64, 64, 16)]:
             U, g, _ = setup(dims, "smooth", 1001, [7])
             vh = int(np.prod(dims)) // 2
             srcs = np.stack([synth.source(dims, 1, seed=2100 + k) for k in range(16)])
+            ns = (1, 2, 4, 8, 16) if dims[3] == 16 else (1, 2, 3, 4, 6, 8, 10, 12, 14, 16)
             for prec, recon in [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12)]:
                 pr = lqs.PREC[prec]
-                for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+                for n in ns:
                     x = lqs.Field.from_lex(ctx, torch.from_numpy(srcs[:n]).to(dev), 1, pr)
                     y = x.like(parity=0)
                     for tuned in (False, True):
@@ -474,7 +532,9 @@ def run_suite(a):
                         ms = event_ms(lambda: lqs.dslash_apply(ctx, g, x, y, recon=recon), 10)
                         emit({"suite": "nmulti", "dims": dims, "prec": prec, "recon": recon, "n": n, "tuned": tuned,
                               "us": round(1e3 * ms, 2), "TFLOPs": round(570 * n * vh / ms / 1e9, 3),
-                              "model_GBps": round(model.hop_model_bytes(pr, recon, n) * vh / ms / 1e6, 1)})
+                              "model_GBps": round(model.hop_model_bytes(pr, recon, n) * vh / ms / 1e6, 1),
+                              "alg_frac_8TBps": round(model.hop_min_bytes(pr, recon, n) * vh / ms / 1e6 / PEAK_HBM_GBPS,
+                                                      3)})
                     ctx.set_tuning(False)
             g.close()
 
@@ -756,26 +816,50 @@ def run_suite(a):
               "min_GBps": round(links * 3 * 144 / ms / 1e6, 1),
               "GFLOPs_fp64": round(links * (13 * 198 + 40) / ms / 1e6, 1),
               "note": "per link 12 SU(3) products for the 6 staples + U V (198 flop each) + TA"})
-        eta = torch.from_numpy(synth.source(dims, -1, seed=3006) / np.sqrt(2)).to(dev)
+        # Thermalisation: molecular-dynamics trajectories accepted unconditionally (u = 0) from
+        # the smooth start, fresh momenta and pseudofermion noise for each.  Then a step-size scan
+        # (one trajectory per step count), and timed trajectories with the Metropolis decision
+        # (u uniform) at the smallest step count whose |dH| stayed below 1.
+        def traj(U_, k, u, nsteps, inner, recon, ftol):
+            Q0 = torch.from_numpy(synth.momenta(dims, seed=4000 + k)).to(dev)
+            eta = torch.from_numpy(synth.source(dims, -1, seed=5000 + k) / np.sqrt(2)).to(dev)
+            return lqs.hmc_trajectory(ctx, dims, U_, Q0, eta, u=u, beta=5.5, mass=0.05, tau=1.0, nsteps=nsteps,
+                                      integrator=lqs.OMELYAN, fermions=1, tol=1e-10, inner_prec=lqs.PREC[inner],
+                                      inner_recon=recon, use_x0=True, force_tol=ftol)
+
+        n_therm = 30
+        t_th = time.perf_counter()
+        for k in range(n_therm):
+            st = traj(Ud, k, 0.0, 10, "f16", 12, 1e-7)
+        torch.cuda.synchronize()
+        emit({"suite": "hmc_24x4_thermalisation", "trajectories": n_therm, "nsteps": 10,
+              "s": round(time.perf_counter() - t_th, 2), "last_dH": st["dH"], "plaquette": st["plaquette"],
+              "note": "accepted unconditionally (u = 0), FP16 inner, force solves to 1e-7"})
+        scan = {}
+        for ns in (20, 40, 80):
+            U0 = Ud.clone()
+            st = traj(U0, 100 + ns, 0.0, ns, "f16", 12, 1e-7)
+            scan[ns] = st["dH"]
+        nsel = min([ns for ns in scan if abs(scan[ns]) < 1.0] or [80])
+        emit({"suite": "hmc_24x4_step_scan", "dH_by_nsteps": scan, "chosen_nsteps": nsel})
+        rng = np.random.default_rng(3100)
         for inner, recon, ftol in (("f64", 18, 0.0), ("f32", 12, 0.0), ("f16", 12, 0.0), ("f16", 12, 1e-7)):
             res = []
-            for k in range(2):
+            for k in range(3):
                 U0 = Ud.clone()
-                Q0 = torch.from_numpy(synth.momenta(dims, seed=3010 + k)).to(dev)
+                u = float(rng.uniform())
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                st = lqs.hmc_trajectory(ctx, dims, U0, Q0, eta, u=0.5, beta=5.5, mass=0.05, tau=1.0, nsteps=10,
-                                        integrator=lqs.OMELYAN, fermions=1, tol=1e-10, inner_prec=lqs.PREC[inner],
-                                        inner_recon=recon, use_x0=True, force_tol=ftol)
+                st = traj(U0, 200 + k, u, nsel, inner, recon, ftol)
                 torch.cuda.synchronize()
                 res.append((time.perf_counter() - t0, st))
-            t_, st = res[-1]
-            emit({"suite": "hmc_24x4", "inner": inner, "recon": recon, "force_tol": ftol,
-                  "s_per_trajectory": round(t_, 4),
-                  "cg_solves": st["cg_solves"], "cg_iters": st["cg_iters"], "dH": st["dH"],
-                  "plaquette": st["plaquette"], "status": st["status"],
-                  "note": "Omelyan, 10 steps, tau 1, beta 5.5, m 0.05, solves to 1e-10 (force solves to "
-                          "force_tol if set), warm-started"})
+            emit({"suite": "hmc_24x4", "inner": inner, "recon": recon, "force_tol": ftol, "nsteps": nsel,
+                  "s_per_trajectory": round(float(np.mean([t_ for t_, _ in res[1:]])), 4),
+                  "cg_solves": res[-1][1]["cg_solves"], "cg_iters": res[-1][1]["cg_iters"],
+                  "dH": [r_["dH"] for _, r_ in res], "accepted": [r_["accepted"] for _, r_ in res],
+                  "plaquette": res[-1][1]["plaquette"], "status": res[-1][1]["status"],
+                  "note": "thermalised links, Omelyan, tau 1, beta 5.5, m 0.05, solves to 1e-10 "
+                          "(force solves to force_tol if set), warm-started"})
 
 
 if __name__ == "__main__":

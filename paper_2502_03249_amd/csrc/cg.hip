@@ -106,6 +106,26 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 }
 
 // ---------------------------------------------------------------------------
+// The new search direction r + beta p at site cb, in the accumulation
+// precision (one fused multiply-add per component).
+
+template <int P, int PA>
+__device__ __forceinline__ V3<typename RealOf<PA>::type> direction_at(const char *r, const char *p, int64_t vh, int cb,
+                                                                      typename RealOf<PA>::type beta)
+{
+    typedef typename RealOf<PA>::type TA;
+    const V3<TA> rv = SpinorIO<PA>::load(r, vh, cb);
+    const V3<TA> pv = vcast<TA>(SpinorIO<P>::load(p, vh, cb));
+    V3<TA> o;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o.c[a].re = fused(beta, pv.c[a].re, rv.c[a].re);
+        o.c[a].im = fused(beta, pv.c[a].im, rv.c[a].im);
+    }
+    return o;
+}
+
+// ---------------------------------------------------------------------------
 // 2. q = m^2 p - D_eo t, <p, q>  (output parity even; t odd)
 
 // FP16 storage: left alone the compiler gives the one-vector kernel 120 VGPRs
@@ -114,13 +134,13 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 template <int P, int R, int K, int LF>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(P == F16 ? 6 : 1)))
 normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
-                                                         int64_t stride, double m2, CgState *st, double *partials,
-                                                         int max_blocks, int nrhs, int ngroups, int tpx)
+                                                         int64_t stride, CgState *st, double *partials,
+                                                         int max_blocks, int nrhs, int ngroups, int tmap)
 {
     typedef typename RealOf<P>::type T;
-    int tile, grp;
-    tile_group(ngroups, tpx, tile, grp);
-    if (tile * (int)blockDim.x >= g.vh) return;  // padding tile (whole block)
+    int grp;
+    const int tile = tile_group(ngroups, tmap, g.n[3], grp);
+    if (tile < 0 || tile * (int)blockDim.x >= g.vh) return;  // padding tile (whole block)
     const int cb = tile * blockDim.x + threadIdx.x;
     const bool valid = cb < g.vh;
     const int r0 = grp * K;
@@ -149,11 +169,12 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
         dot[j] = 0.0;
         if (!act[j]) continue;
         const V3<T> pv = SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
+        const T m2 = (T)st[r0 + j].m2;
         V3<T> qv;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            qv.c[a].re = (T)m2 * pv.c[a].re - acc[j].c[a].re;
-            qv.c[a].im = (T)m2 * pv.c[a].im - acc[j].c[a].im;
+            qv.c[a].re = m2 * pv.c[a].re - acc[j].c[a].re;
+            qv.c[a].im = m2 * pv.c[a].im - acc[j].c[a].im;
             dot[j] += (double)pv.c[a].re * (double)qv.c[a].re + (double)pv.c[a].im * (double)qv.c[a].im;
         }
         SpinorIO<P>::store(q + (r0 + j) * stride, g.vh, cb, qv);
@@ -244,17 +265,8 @@ __global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char 
     const T beta = (T)S.beta;
     r += rhs * sa;
     p += rhs * si;
-    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
-        const V3<T> rv = SpinorIO<PA>::load(r, vh, cb);
-        const V3<T> pv = vcast<T>(SpinorIO<PI>::load(p, vh, cb));
-        V3<T> o;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            o.c[a].re = rv.c[a].re + beta * pv.c[a].re;
-            o.c[a].im = rv.c[a].im + beta * pv.c[a].im;
-        }
-        SpinorIO<PI>::store(p, vh, cb, vcast<TI>(o));
-    }
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x)
+        SpinorIO<PI>::store(p, vh, cb, vcast<TI>(direction_at<PI, PA>(r, p, vh, cb, beta)));
 }
 
 // ---------------------------------------------------------------------------
@@ -285,7 +297,7 @@ __global__ void __launch_bounds__(BLAS_BLOCK) accumulate_kernel(int vh, double *
 // gate_mode as in gate_state (0: all right-hand sides).
 template <int R, int PA, int K, int LF>
 __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const char *t64, const char *x,
-                                                       const char *b, char *r, int64_t sa, double m2, CgState *st,
+                                                       const char *b, char *r, int64_t sa, CgState *st,
                                                        double *partials, int max_blocks, int nrhs, int gate_mode,
                                                        int mode)
 {
@@ -314,6 +326,7 @@ __global__ void __launch_bounds__(512) residual_kernel(Geom g, LinkRef L, const 
         if (!act[j]) continue;
         const V3<double> xv = SpinorIO<F64>::load(x + (r0 + j) * s64, g.vh, cb);
         const V3<double> bv = SpinorIO<F64>::load(b + (r0 + j) * s64, g.vh, cb);
+        const double m2 = st[r0 + j].m2;
         V3<double> rv;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -431,14 +444,14 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const Geom &g = gauge.g;
     const int64_t stride = field_bytes(g, P, 1);
     const LinkRef L = gauge.ref(P, R);
-    const int tiles = (g.vh + sh.block - 1) / sh.block, G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
-    const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
-    const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
-    const double m2 = v.mass * v.mass;
+    const int G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
+    const int tmap = tile_map(g, sh.block, sh.xcd_slab);
+    const dim3 grid(tile_map_blocks(g, sh.block, tmap, G));
     const size_t lds = hop_lds_bytes(g, P, sh.rhs_per_thread, sh);
 #define LQS_ND(K, LF)                                                                                             \
     hipLaunchKernelGGL((normal_dot_kernel<P, R, K, LF>), grid, dim3(sh.block), lds, s, g, L, (const char *)v.t,   \
-                       (const char *)v.p, (char *)v.q, stride, m2, v.state, v.partials, v.max_blocks, v.nrhs, G, tpx)
+                       (const char *)v.p, (char *)v.q, stride, v.state, v.partials,          \
+                       v.max_blocks, v.nrhs, G, tmap)
 #define LQS_ND_LF(LF)                                                                                            \
     if (sh.rhs_per_thread == 1) LQS_ND(1, LF);                                                                   \
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \
@@ -499,10 +512,9 @@ static void launch_residual_k(const Gauge &gauge, const CgVectors &v, int gate_m
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (default_hop_shape(L, v.nrhs).stream_links ? LF_STREAM : 0);
     const int64_t sa = field_bytes(g, PA, 1);
     char *r = (char *)(mode == 2 ? nullptr : v.r);
-    const double m2 = v.mass * v.mass;
 #define LQS_RES(LF)                                                                                               \
     hipLaunchKernelGGL((residual_kernel<R, PA, K, LF>), grid, dim3(block), 0, s, g, L, (const char *)v.t64,       \
-                       (const char *)v.x, (const char *)v.b, r, sa, m2, v.state, v.partials, v.max_blocks, v.nrhs,  \
+                       (const char *)v.x, (const char *)v.b, r, sa, v.state, v.partials, v.max_blocks, v.nrhs,  \
                        gate_mode, mode)
     switch (lf) {
     case 0: LQS_RES(0); break;
@@ -593,13 +605,20 @@ void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_
     }
 }
 
+// Launch shape of the CG hop (tuned, else the default)
+static LaunchShape cg_hop_shape(Ctx &ctx, const Gauge &gauge, int prec, int recon, int nrhs)
+{
+    LaunchShape sh = default_hop_shape(gauge.ref(prec, recon), nrhs);
+    if (ctx.tuner) ctx.tuner->lookup(tune_key(ctx, gauge.temporal ? "hop_tg" : "hop", gauge.g, prec, recon, nrhs), sh);
+    return sh;
+}
+
 void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, bool with_reliable)
 {
-    LaunchShape sh = default_hop_shape(gauge.ref(v.prec, v.recon), v.nrhs);
-    LaunchShape shd = sh;
+    const LaunchShape sh = cg_hop_shape(ctx, gauge, v.prec, v.recon, v.nrhs);
+    LaunchShape shd = default_hop_shape(gauge.ref(v.prec, v.recon), v.nrhs);
     if (ctx.tuner) {
         const bool tg = gauge.temporal;
-        ctx.tuner->lookup(tune_key(ctx, tg ? "hop_tg" : "hop", gauge.g, v.prec, v.recon, v.nrhs), sh);
         ctx.tuner->lookup(tune_key(ctx, tg ? "normal_dot_tg" : "normal_dot", gauge.g, v.prec, v.recon, v.nrhs), shd);
     }
     // 1. t = D_oe p
@@ -634,7 +653,7 @@ static bool final_phase(int32_t ph)
 }
 
 // Initial state records of one problem's right-hand sides.
-static void cg_initial_states(const lqs_cg_params &prm, int nrhs, CgState *out)
+static void cg_initial_states(const lqs_cg_params &prm, int nrhs, const double *mass, CgState *out)
 {
     const bool mixed = prm.inner_prec != F64;
     const int rel_interval = mixed ? (prm.reliable_interval > 0 ? prm.reliable_interval : 100) : 0;
@@ -647,6 +666,7 @@ static void cg_initial_states(const lqs_cg_params &prm, int nrhs, CgState *out)
         S.rel_interval = rel_interval;
         S.max_iter = prm.max_iter;
         S.phase = CG_RUNNING;
+        S.m2 = mass[r] * mass[r];
         out[r] = S;
     }
 }
@@ -717,6 +737,7 @@ struct CgRun {
 
     // Buffers come from the context's workspace, or, when `arena` is set,
     // are carved from that preallocated device region (no allocation).
+    std::vector<double> masses;  // per right-hand side (empty: pb.mass for all)
     char *arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
     CgState *arena_host = nullptr;  // host mirror (two records per rhs) with an arena
@@ -776,7 +797,10 @@ struct CgRun {
             hs[0] = (CgState *)host;
             hs[1] = (CgState *)(host + sbytes);
         }
-        cg_initial_states(prm, nrhs, hs[0]);
+        std::vector<double> mass(nrhs, pb.mass);
+        if (!masses.empty()) mass = masses;
+        LQS_REQUIRE((int)mass.size() == nrhs, LQS_EINVAL, "one mass per right-hand side");
+        cg_initial_states(prm, nrhs, mass.data(), hs[0]);
         if (!arena) {
             LQS_HIP(hipEventCreate(&tev[0]));
             LQS_HIP(hipEventCreate(&tev[1]));
@@ -887,7 +911,8 @@ struct CgRun {
 
 }  // namespace
 
-void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s)
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s,
+                  const std::vector<double> *masses)
 {
     // graphs are captured on a side stream (the caller's stream may be the
     // null stream, which cannot be captured), forked from and joined into s
@@ -909,6 +934,7 @@ void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs
         }
         CgRun run(ctx, pb, prm, stats, rs, "", std::chrono::steady_clock::now());
         run.use_graph = graphs;
+        if (masses) run.masses = *masses;
         run.setup();
         try {
             while (!run.done) {

@@ -375,6 +375,17 @@ template <> struct SpinorIO<F32> {
     }
 };
 
+// binary16 of a binary32 value held in a register.  The empty asm keeps the
+// compiler from folding the multiply that produced x and this conversion into
+// one mixed-precision instruction that rounds once: it does so in some kernels
+// and not in others, and the colour-vector store and the in-register round trip
+// below must round identically (binary32, then binary16) everywhere.
+__device__ __forceinline__ half_t to_half(float x)
+{
+    asm volatile("" : "+v"(x));
+    return (half_t)x;
+}
+
 struct alignas(16) SpH {
     half_t h[6];
     float s;
@@ -393,6 +404,7 @@ template <> struct SpinorIO<F16> {
     }
     // Scale = max |component| of the site; components stored as binary16 of
     // value / scale (round to nearest even); an all-zero site stores scale 0.
+    // value * (1 / scale) is rounded to binary32 and then to binary16 (to_half).
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<float> &v)
     {
         (void)vh;
@@ -403,8 +415,8 @@ template <> struct SpinorIO<F16> {
         SpH q;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            q.h[2 * a] = (half_t)(v.c[a].re * inv);
-            q.h[2 * a + 1] = (half_t)(v.c[a].im * inv);
+            q.h[2 * a] = to_half(v.c[a].re * inv);
+            q.h[2 * a + 1] = to_half(v.c[a].im * inv);
         }
         q.s = m;
         ((W16 *)base)[cb] = bitcast<W16>(q);
@@ -427,7 +439,7 @@ template <> struct Roundtrip<F16> {
         V3<float> w;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            w.c[a] = {(float)(half_t)(v.c[a].re * inv) * m, (float)(half_t)(v.c[a].im * inv) * m};
+            w.c[a] = {(float)to_half(v.c[a].re * inv) * m, (float)to_half(v.c[a].im * inv) * m};
         return w;
     }
 };

@@ -15,13 +15,13 @@ namespace lqs {
 template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
-                                                  const CgState *gate, int gate_mode, int ngroups, int tpx)
+                                                  const CgState *gate, int gate_mode, int ngroups, int tmap)
 {
     typedef typename RealOf<P>::type T;
-    int tile, grp;
-    tile_group(ngroups, tpx, tile, grp);
+    int grp;
+    const int tile = tile_group(ngroups, tmap, g.n[3], grp);
     const int c0 = tile * blockDim.x;
-    if (c0 >= g.vh) return;  // padding tile (whole block)
+    if (tile < 0 || c0 >= g.vh) return;  // padding tile (whole block)
     const int cb = c0 + threadIdx.x;
     const int r0 = grp * K;
     bool active[K];
@@ -57,14 +57,14 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
                      const CgState *gate, int gate_mode, LaunchShape sh, hipStream_t s)
 {
     const int64_t stride = field_bytes(g, P, 1);
-    const int tiles = (g.vh + sh.block - 1) / sh.block, G = (nrhs + K - 1) / K;
-    const int tpx = slab_tiles_per_xcd(g, sh.block, sh.xcd_slab);
-    const dim3 grid(tile_group_blocks(tiles, G, tpx != 0));
+    const int G = (nrhs + K - 1) / K;
+    const int tmap = tile_map(g, sh.block, sh.xcd_slab);
+    const dim3 grid(tile_map_blocks(g, sh.block, tmap, G));
     const size_t lds = hop_lds_bytes(g, P, K, sh);
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
 #define LQS_HOP(DAG, LF)                                                                                         \
     hipLaunchKernelGGL((hop_kernel<P, R, K, DAG, LF>), grid, dim3(sh.block), lds, s, g, L, parity, nrhs,          \
-                       (const char *)in, stride, (char *)out, stride, gate, gate_mode, G, tpx)
+                       (const char *)in, stride, (char *)out, stride, gate, gate_mode, G, tmap)
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
     else LQS_HOP(false, LF)
@@ -106,18 +106,21 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
     else launch_pr<F16, 12>(g, L, dagger, parity, nrhs, in, out, gate, gate_mode, sh, s);
 }
 
-// Shapes the autotuner picked most often on 32^4 and 32^3x8 (every
-// precision): 4 right-hand sides per thread in 64-thread blocks from 4
-// vectors on, 2 per thread in 128-thread blocks for 2-3 vectors.  Links are
-// streamed when their footprint exceeds STREAM_LINK_BYTES and one group of
-// right-hand sides covers all of them; with several groups the blocks of one
-// site tile reuse the links from L2 (see tile_group) and cached loads win.
+// Default shapes from measured sweeps on 32^4, 32^3x8 and 64^3x16: from 4
+// vectors on, 4 right-hand sides per thread in 128-thread blocks with the
+// time-inner block -> tile map (at 64^3x16 with 16 vectors 6-17 % faster than
+// 64-thread blocks in lexicographic order, equal on 32^4); 2 per thread in
+// 128-thread blocks for 2-3 vectors.  Links are streamed when their footprint
+// exceeds STREAM_LINK_BYTES and one group of right-hand sides covers all of
+// them; with several groups the blocks of one site tile reuse the links from
+// L2 (see tile_group) and cached loads win.
 LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
     LaunchShape sh;
     if (nrhs >= 4) {
-        sh.block = 64;
+        sh.block = 128;
         sh.rhs_per_thread = 4;
+        sh.xcd_slab = 2;
     } else if (nrhs >= 2) {
         sh.block = 128;
         sh.rhs_per_thread = 2;

@@ -19,37 +19,54 @@ namespace lqs {
 enum { LF_TEMPORAL = 1, LF_STREAM = 2, LF_LDS = 4 };
 
 // Block -> (site tile, right-hand-side group).  Consecutive block indices go
-// to the 8 XCDs in turn, each with its own L2; two maps build on that:
-//  - round robin (tpx == 0): tile t runs on XCD t mod 8, and the G blocks of
+// to the 8 XCDs in turn, each with its own L2; three maps build on that
+// (tmap, from tile_map below):
+//  - round robin (tmap == 0): tile t runs on XCD t mod 8, and the G blocks of
 //    one tile are 8 block indices apart, so they run on the same XCD in close
 //    succession and the links they share come from HBM once, then from that
 //    XCD's L2.  Neighbour tiles a multiple of 8 tiles away share the XCD.
-//  - slab (tpx > 0): XCD x sweeps the contiguous tiles [x tpx, (x + 1) tpx),
-//    so every neighbour except those across the slab ends is in its L2.
-// Both grids have ceil(tiles / 8) * 8 * G blocks (exactly `tiles` for the
-// round-robin map with G == 1, where it is the identity); tiles past the last
-// are empty.
-__device__ __forceinline__ void tile_group(int G, int tpx, int &tile, int &grp)
+//  - slab (tmap > 0 tiles per XCD): XCD x sweeps the contiguous tiles
+//    [x tmap, (x + 1) tmap), so every neighbour except those across the slab
+//    ends is in its L2.
+//  - time-inner (tmap < 0, -tmap = S tiles per time slice): the tiles s of a
+//    time slice go to XCD s mod 8, and each XCD runs all Nt time slices of one
+//    of its tiles before the next one, so the t neighbours of a tile were read
+//    one tile earlier and the z neighbours a few tiles earlier, on the same
+//    XCD; the lexicographic sweep instead reads a t neighbour a whole time
+//    slice later, which with several right-hand sides no longer fits in L2.
+// Returns the tile, or -1 for a padding block.  Grids: tile_map_blocks.
+__device__ __forceinline__ int tile_group(int G, int tmap, int nt, int &grp)
 {
     const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
     grp = q % G;
-    tile = tpx ? xcd * tpx + q / G : (q / G) * 8 + xcd;
-}
-
-inline unsigned tile_group_blocks(int tiles, int G, bool slab)
-{
-    return (G == 1 && !slab) ? tiles : ((tiles + 7) / 8) * 8 * G;
+    const int qq = q / G;
+    if (tmap == 0) return qq * 8 + xcd;
+    if (tmap > 0) return xcd * tmap + qq;
+    const int S = -tmap, s = (qq / nt) * 8 + xcd;
+    return s < S ? (qq % nt) * S + s : -1;
 }
 
 // The round-robin map keeps the z and t neighbours of a tile on its XCD when
 // the z stride (Nx Ny / 2 sites) is a whole number of 8-tile strides; the
-// slab map is used otherwise.
+// slab map is used otherwise (mode -1).  Modes 0, 1, 2 ask for round robin,
+// slab and time-inner; time-inner needs whole tiles per time slice and falls
+// back to the automatic choice otherwise.
 inline bool xcd_slab_auto(const Geom &g, int block) { return ((int64_t)g.n[0] * g.n[1] / 2) % (8 * block) != 0; }
-inline int slab_tiles_per_xcd(const Geom &g, int block, int xcd_slab)
+inline int tile_map(const Geom &g, int block, int mode)
 {
     const int tiles = (g.vh + block - 1) / block;
-    const bool slab = xcd_slab < 0 ? xcd_slab_auto(g, block) : xcd_slab != 0;
+    const int64_t slice = (int64_t)g.vh / g.n[3];
+    if (mode == 2 && slice % block == 0) return -(int)(slice / block);
+    const bool slab = (mode == 2 || mode < 0) ? xcd_slab_auto(g, block) : mode != 0;
     return slab ? (tiles + 7) / 8 : 0;
+}
+inline unsigned tile_map_blocks(const Geom &g, int block, int tmap, int G)
+{
+    const int tiles = (g.vh + block - 1) / block;
+    if (tmap == 0 && G == 1) return tiles;
+    if (tmap >= 0) return ((tiles + 7) / 8) * 8 * G;
+    const int S = -tmap;
+    return ((S + 7) / 8) * 8 * g.n[3] * G;
 }
 
 // Gates of the CG kernels on the state of one right-hand side.  0: always;

@@ -62,6 +62,7 @@ struct CgState {
     double delta2;     // reliable-update threshold delta^2
     double true_r2;    // last FP64 |b - M x|^2
     double b2;         // |b|^2
+    double m2;         // mass^2 of this right-hand side's operator M = m^2 - D_eo D_oe
     int32_t phase;
     int32_t iters;
     int32_t since_rel;
@@ -198,7 +199,7 @@ struct CgVectors {
     int acc_prec;           // precision of x_lo and r (F64 in the plain solver)
     int recon;              // inner link format
     int nrhs;
-    double mass;
+    double mass;            // (the kernels read each right-hand side's m^2 from its CgState)
     void *p, *q, *t;        // p, q even; t odd
     void *r, *xlo;          // iterated residual and inner solution (even)
     double *x, *b, *rhi;    // FP64: solution, source, FP64 residual (even)
@@ -235,7 +236,9 @@ void *noalloc_scratch(int device);
 void cg_solve_noalloc_impl(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats,
                            hipStream_t s);
 // cg.hip: one problem with the multi-kernel iteration (returns when done)
-void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s);
+// masses: one per right-hand side (null: pb.mass for all)
+void cg_solve_one(Ctx &ctx, const lqs_problem &pb, const lqs_cg_params &prm, lqs_cg_stats *stats, hipStream_t s,
+                  const std::vector<double> *masses = nullptr);
 // several problems, each on its own side stream, iterated concurrently
 void cg_solve_concurrent(Ctx &ctx, int nprob, const lqs_problem *probs, const lqs_cg_params &prm,
                          lqs_cg_stats *stats, hipStream_t s);

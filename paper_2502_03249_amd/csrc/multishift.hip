@@ -19,9 +19,16 @@
 // advances all solutions, a finalize for beta, and one kernel that advances
 // all search directions.  The recurrence runs in FP64, or with the search
 // directions and the operator in FP32 or FP16 storage and the residual and
-// the solutions in FP32 (copied into the caller's FP64 fields at the end).  Afterwards every mass gets an FP64
-// true-residual check that also refines it with a warm-started CG (mixed
-// precision when the recurrence was) if the recurrence left it above tol.
+// the solutions in FP32.  In the mixed recurrence the base system takes the
+// reliable updates of the mixed-precision CG: every K iterations, or when
+// |r| fell below delta max |r|, every solution is added into the caller's
+// FP64 field (its FP32 part restarts from zero), the base residual is
+// replaced by b - M_0 x_0 computed in FP64, and beta and every beta_i are
+// recomputed from it (the shifted residuals stay zeta_i r, which the
+// replacement keeps to the accuracy of the FP64 residual).  Afterwards every
+// mass gets an FP64 true-residual check that also refines it with a
+// warm-started CG (mixed precision when the recurrence was) if the
+// recurrence left it above tol.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -31,6 +38,7 @@
 namespace lqs {
 
 void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape sh, hipStream_t s);
+void cg_residual_group(Ctx &ctx, const Gauge &gauge, const CgVectors &v, int gate_mode, int mode, hipStream_t s);
 
 static constexpr int MS_MAX = 16;
 static constexpr int MS_BLOCK = 256;
@@ -44,8 +52,10 @@ struct ShiftState {
 };
 
 struct ShiftPtrs {
-    char *x[MS_MAX];                 // solution of each shifted system (storage PR)
-    char *p[MS_MAX];                 // search direction of each shifted system (storage PI)
+    char *x[MS_MAX + 1];             // solution of each shifted system (storage PR)
+    char *p[MS_MAX + 1];             // search direction of each shifted system (storage PI)
+    double *x64[MS_MAX + 1];         // mixed recurrence: the caller's FP64 solution it is added into
+                                     // (entry nshift: the base, for the final flush)
 };
 
 __global__ void __launch_bounds__(1024) ms_finalize_dot(CgState *base, ShiftState *sh, int nshift,
@@ -151,8 +161,55 @@ __global__ void __launch_bounds__(1024) ms_finalize_update(CgState *base, ShiftS
         if (T.zeta * T.zeta * r2 <= S.stop2) T.active = 0;
         any |= T.active;
     }
-    if (!isfinite(r2)) S.phase = CG_NONFINITE;
-    else if ((r2 <= S.stop2 && !any) || S.iters >= S.max_iter) S.phase = CG_INNER_DONE;
+    S.since_rel += 1;
+    if (!isfinite(r2)) {
+        S.phase = CG_NONFINITE;
+        return;
+    }
+    if (r2 > S.max_rho) S.max_rho = r2;
+    if ((r2 <= S.stop2 && !any) || S.iters >= S.max_iter) {
+        S.phase = CG_INNER_DONE;
+        // mixed: the FP64 residual of the base decides (and resumes when it is above the target)
+        if (S.rel_interval > 0) S.reliable_pending = 1;
+        return;
+    }
+    if (S.rel_interval > 0 && (S.since_rel >= S.rel_interval || r2 < S.delta2 * S.max_rho)) S.reliable_pending = 1;
+}
+
+// Mixed recurrence, reliable update: add every FP32 solution into its FP64
+// field and restart it from zero (gated: the base's update is pending, or
+// gated = 0 at the end of the recurrence).
+template <int PR>
+__global__ void __launch_bounds__(MS_BLOCK) ms_accumulate(int vh, const ShiftPtrs *ptr, int nshift, const CgState *base,
+                                                          int gated)
+{
+    typedef typename RealOf<PR>::type TR;
+    if (gated && !base->reliable_pending) return;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x)
+        for (int i = 0; i < nshift; ++i) {
+            V3<double> xv = SpinorIO<F64>::load(ptr->x64[i], vh, cb);
+            const V3<double> lv = vcast<double>(SpinorIO<PR>::load(ptr->x[i], vh, cb));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xv.c[c].re += lv.c[c].re;
+                xv.c[c].im += lv.c[c].im;
+            }
+            SpinorIO<F64>::store(ptr->x64[i], vh, cb, xv);
+            SpinorIO<PR>::store(ptr->x[i], vh, cb, vzero<TR>());
+        }
+}
+
+// after a reliable update of the base: beta_i = beta (zeta_{k+1} / zeta_k)^2
+// with the base's new beta (the same value ms_finalize_update set otherwise)
+__global__ void ms_rebeta(const CgState *base, ShiftState *sh, int nshift)
+{
+    if (threadIdx.x != 0 || base->phase != CG_RUNNING) return;
+    for (int i = 0; i < nshift; ++i) {
+        ShiftState &T = sh[i];
+        if (!T.active) continue;
+        const double ratio = T.zeta / T.zeta_prev;
+        T.beta = base->beta * ratio * ratio;
+    }
 }
 
 // p_0 = r + beta p_0; p_i = zeta_i r + beta_i p_i for active shifts
@@ -220,6 +277,7 @@ __global__ void __launch_bounds__(1024) ms_finalize_init(CgState *base, const do
     S.b2 = b2;
     S.stop2 *= b2;
     S.rho = b2;
+    S.max_rho = b2;
     S.true_r2 = b2;
     S.alpha = 1.0;  // alpha_{-1}
     S.beta = 0.0;   // beta_{-1}
@@ -260,9 +318,11 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     std::vector<char *> xr(nmass);
     for (int i = 0; i < nmass; ++i)
         xr[i] = PR == F64 ? (char *)x[i] : (char *)ctx.workspace("ms.x" + std::to_string(i), fr);
-    v.x = (double *)xr[base];
+    const bool mixed = PR != F64;
+    v.x = mixed ? x[base] : (double *)xr[base];
     v.xlo = xr[base];
     v.b = (double *)b;
+    v.t64 = mixed ? ctx.workspace("ms.t64", field_bytes(g, F64, 1)) : nullptr;
     v.max_blocks = cg_partials_needed(gauge, 1);
     v.partials = (double *)ctx.workspace("ms.partials", sizeof(double) * (size_t)v.max_blocks);
     v.state = (CgState *)ctx.workspace("ms.state", sizeof(CgState));
@@ -270,6 +330,7 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     std::vector<ShiftState> hsh(nshift);
     for (int k = 0; k < nshift; ++k) {
         hp.x[k] = xr[shifts[k]];
+        hp.x64[k] = x[shifts[k]];
         hp.p[k] = (char *)ctx.workspace("ms.p" + std::to_string(k), fi);
         ShiftState &T = hsh[k];
         T = ShiftState{};
@@ -280,13 +341,27 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     ShiftPtrs *dp = (ShiftPtrs *)ctx.workspace("ms.ptrs", sizeof(ShiftPtrs));
     ShiftState *dsh = (ShiftState *)ctx.workspace("ms.shifts", sizeof(ShiftState) * (nshift > 0 ? nshift : 1));
     CgState S{};
+    S.m2 = masses[base] * masses[base];
     S.stop2 = prm.tol * prm.tol;
     S.max_iter = prm.max_iter;
     S.phase = CG_RUNNING;
+    if (mixed) {
+        S.rel_interval = prm.reliable_interval > 0 ? prm.reliable_interval : 100;
+        const double delta = prm.reliable_delta > 0 ? prm.reliable_delta : default_reliable_delta(PI);
+        S.delta2 = delta * delta;
+    }
+    // the base as one more entry of the accumulation list (its FP32 and FP64 solutions)
+    ShiftPtrs hall = hp;
+    hall.x[nshift] = xr[base];
+    hall.x64[nshift] = x[base];
+    ShiftPtrs *dall = (ShiftPtrs *)ctx.workspace("ms.ptrs_all", sizeof(ShiftPtrs));
+    if (mixed) LQS_HIP(hipMemcpyAsync(dall, &hall, sizeof(ShiftPtrs), hipMemcpyHostToDevice, s));
     LQS_HIP(hipMemcpyAsync(dp, &hp, sizeof(ShiftPtrs), hipMemcpyHostToDevice, s));
     if (nshift) LQS_HIP(hipMemcpyAsync(dsh, hsh.data(), sizeof(ShiftState) * nshift, hipMemcpyHostToDevice, s));
     LQS_HIP(hipMemcpyAsync(v.state, &S, sizeof(CgState), hipMemcpyHostToDevice, s));
 
+    if (mixed)
+        for (int i = 0; i < nmass; ++i) LQS_HIP(hipMemsetAsync(x[i], 0, field_bytes(g, F64, 1), s));
     int blocks = (vh + MS_BLOCK - 1) / MS_BLOCK;
     if (blocks > 1024) blocks = 1024;
 #define LQS_MS_PREC(STMT)                                                                                         \
@@ -322,6 +397,13 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
                                            nshift, (const CgState *)v.state, (const ShiftState *)dsh, v.partials));
             hipLaunchKernelGGL(ms_finalize_update, dim3(1), dim3(1024), 0, s, v.state, dsh, nshift,
                                (const double *)v.partials, blocks);
+            if (mixed && (i & 3) == 3) {
+                // reliable update (gated on the base's pending flag)
+                hipLaunchKernelGGL((ms_accumulate<F32>), dim3(blocks), dim3(MS_BLOCK), 0, s, vh, (const ShiftPtrs *)dp,
+                                   nshift, (const CgState *)v.state, 1);
+                cg_residual_group(ctx, gauge, v, 2, 0, s);
+                hipLaunchKernelGGL(ms_rebeta, dim3(1), dim3(64), 0, s, (const CgState *)v.state, dsh, nshift);
+            }
             LQS_MS_PREC(hipLaunchKernelGGL((ms_pupdate<P_I, P_R>), dim3(blocks), dim3(MS_BLOCK), 0, s, vh,
                                            (const char *)v.r, (char *)v.p, (const ShiftPtrs *)dp, nshift,
                                            (const CgState *)v.state, (const ShiftState *)dsh));
@@ -336,19 +418,39 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     LQS_HIP(hipStreamSynchronize(s));
 
 #undef LQS_MS_PREC
-    if (PR != F64)
-        for (int i = 0; i < nmass; ++i) launch_convert(g, 1, PR, xr[i], F64, x[i], s);
+    if (mixed) {
+        hipLaunchKernelGGL((ms_accumulate<F32>), dim3(blocks), dim3(MS_BLOCK), 0, s, vh, (const ShiftPtrs *)dall,
+                           nshift + 1, (const CgState *)v.state, 0);
+        LQS_HIP(hipGetLastError());
+    }
     // every mass: FP64 true residual from its own solution, refined by a
     // warm-started CG (in the recurrence's precision, with reliable updates)
-    // when the shared recurrence ended above the target
+    // when the shared recurrence ended above the target.  The masses are
+    // refined together as one block of CGs with one mass per column (up to 16
+    // per block), so every hop reads the links once for all masses still
+    // refining; a column that starts below the target does no iteration.
     lqs_cg_params rp = prm;
     rp.use_x0 = 1;
     rp.persistent = 0;
+    const int64_t f64 = field_bytes(g, F64, 1);
+    const int per_block = std::min(nmass, 16);
+    char *xb = (char *)ctx.workspace("ms.xblock", f64 * per_block);
+    char *bb = (char *)ctx.workspace("ms.bblock", f64 * per_block);
+    for (int c0 = 0; c0 < nmass; c0 += per_block) {
+        const int n = std::min(per_block, nmass - c0);
+        for (int i = 0; i < n; ++i) {
+            LQS_HIP(hipMemcpyAsync(xb + i * f64, x[c0 + i], f64, hipMemcpyDeviceToDevice, s));
+            LQS_HIP(hipMemcpyAsync(bb + i * f64, b, f64, hipMemcpyDeviceToDevice, s));
+        }
+        lqs_problem pb{static_cast<const lqs_gauge *>(&gauge), masses[c0], n, (const double *)bb, (double *)xb};
+        const std::vector<double> mcol(masses + c0, masses + c0 + n);
+        cg_solve_one(ctx, pb, rp, stats + c0, s, &mcol);
+        for (int i = 0; i < n; ++i)
+            LQS_HIP(hipMemcpyAsync(x[c0 + i], xb + i * f64, f64, hipMemcpyDeviceToDevice, s));
+    }
+    LQS_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < nmass; ++i) {
-        lqs_problem pb{static_cast<const lqs_gauge *>(&gauge), masses[i], 1, b, x[i]};
         const int shared = (i == base) ? hs.iters : hsh[std::find(shifts.begin(), shifts.end(), i) - shifts.begin()].iters;
-        rp.max_iter = prm.max_iter;
-        cg_solve_one(ctx, pb, rp, &stats[i], s);
         stats[i].restarts += stats[i].iters > 0 ? 1 : 0;
         stats[i].iters += shared;
         if (hs.phase == CG_NONFINITE) stats[i].status = LQS_ENONFINITE;

@@ -54,7 +54,7 @@ bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) cons
     const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld);
     if (n < 2) return false;
     if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1) ||
-        !(sl >= -1 && sl <= 1) || !(ld == 0 || ld == 1))
+        !(sl >= -1 && sl <= 2) || !(ld == 0 || ld == 1))
         return false;
     out.block = b;
     out.rhs_per_thread = k;
@@ -143,6 +143,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
             S = CgState{};
             S.phase = CG_RUNNING;
             S.rho = 1.0;
+            S.m2 = v.mass * v.mass;
         }
         v.state = st;
     }
@@ -186,6 +187,10 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LaunchShape flip = best_shape;
     flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
     consider(flip);
+    // and the time-inner map, where whole tiles make up a time slice
+    LaunchShape tin = best_shape;
+    tin.xcd_slab = 2;
+    if (tile_map(g, tin.block, 2) < 0) consider(tin);
     // then the kernel with its x/y neighbours staged through LDS, where the window fits
     LaunchShape staged = best_shape;
     staged.lds = 1;

@@ -44,12 +44,12 @@ def arithmetic_intensity(prec, recon=18, nrhs=1, links_per_site=8):
     return hop_flops(nrhs) / hop_model_bytes(prec, recon, nrhs, links_per_site)
 
 
-def cg_iteration_bytes(prec, acc_prec, recon=18):
+def cg_iteration_bytes(prec, acc_prec, recon=18, links_per_site=8):
     """Algorithmic HBM bytes per even site of one CG iteration (four kernels).
 
     hop t = D_oe p: links + p + t; hop q = m^2 p - D_eo t: links + t + p + q;
     update: x, r read and written, p and q read; p = r + beta p: r, p read, p written.
     """
-    L = 8 * link_bytes(prec, recon)
+    L = links_per_site * link_bytes(prec, recon)
     s, a = spinor_bytes(prec), spinor_bytes(acc_prec)
     return (L + 2 * s) + (L + 3 * s) + (4 * a + 2 * s) + (a + 2 * s)

@@ -51,6 +51,6 @@ def test_traffic_is_gated_on_the_hop_sources(monkeypatch):
     t = _traffic()
     if t["hop_f16_12"]["src_hash"] == bench.src_hash():
         assert bench.traffic_for("hop_f16_12", VH_64x16) == t["hop_f16_12"]["bytes_per_launch"]
-    monkeypatch.setattr(bench, "src_hash", lambda: "0" * 16)
+    monkeypatch.setattr(bench, "src_hash", lambda sources=None: "0" * 16)
     assert bench.traffic_for("hop_f16_12", VH_64x16) is None
     assert bench.traffic_for("no_such_kernel", VH_64x16) is None

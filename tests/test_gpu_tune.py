@@ -282,3 +282,33 @@ def test_lds_staged_temporal_gauge_hop(tmp_path):
     for k in range(3):
         want = oracle.dslash(dims, Uf, srcs[k], 0)
         assert rel(outs[1][0][k], want) <= 1e-12 and rel(outs[1][1][k], want) <= 2e-6
+
+
+@pytest.mark.parametrize("prec,recon", [(lqs.F16, 12), (lqs.F64, 18)])
+def test_lds_staged_hop_in_cg_two_columns(tmp_path, prec, recon):
+    """A CG whose hop stages its input through LDS gives the unstaged solve's bits, iteration
+    counts and reliable updates in FP16 storage and FP64, for two columns that converge at
+    different iterations (the first idles behind its FP64 check while the other continues)."""
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "smooth", seed=96, eps=0.3)
+    b = np.stack([synth.source(dims, 0, seed=960), 1e-3 * synth.source(dims, 0, seed=961)])
+    cache = str(tmp_path / "tune.json")
+    runs = []
+    for ld in (0, 1):
+        key = "|".join([torch.cuda.get_device_properties(0).gcnArchName, "hop", "8x8x8x16", "p%d" % prec,
+                        "r%d" % recon, "n2"])
+        with open(cache, "w") as f:
+            json.dump({key: "128,2,0,-1,%d" % ld}, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        g = gauge(ctx, dims, U)
+        bf = field(ctx, dims, b, 0)
+        xf = bf.like().zero_()
+        st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=prec, inner_recon=recon,
+                          reliable_interval=100)
+        x = lex_of(ctx, xf, squeeze=False)
+        for k in range(2):
+            assert st[k]["status"] == 0
+            assert oracle.true_residual(dims, U, mass, b[k], x[k]) <= 1e-10
+        runs.append((x, [(s_["iters"], s_["reliable_updates"]) for s_ in st]))
+        ctx.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
