@@ -263,13 +263,17 @@ lqs_status cg_solve_noalloc(lqs_ctx *ctx, const lqs_problem *prob, const lqs_cg_
  * of the smallest mass m_0).  The shared recurrence keeps its search
  * directions and applies the operator in params->inner_prec (LQS_F64, LQS_F32
  * or LQS_F16 storage, links inner_recon; the residual is FP32 unless FP64) and
- * accumulates every x_i in FP64.  params->persistent must be 0 (else
+ * accumulates every x_i in FP64; in a mixed recurrence the smallest mass takes
+ * the reliable updates of cg_solve (reliable_interval, reliable_delta), each
+ * adding every FP32 solution into its FP64 field.  params->persistent must be 0 (else
  * LQS_EUNSUPPORTED); use_x0 is ignored (x_i start from zero).  b is an FP64
  * native even field (nrhs 1); x is a host array of nmass device pointers to
  * FP64 native even fields, overwritten.  Every x_i is finally checked against
  * its own FP64 true residual and refined, when the shared recurrence ended
  * above tol, by a warm-started CG with the same params (mixed precision with
- * reliable updates unless inner_prec is LQS_F64).  stats: nmass entries; iters
+ * reliable updates unless inner_prec is LQS_F64); the masses are refined
+ * together, one column each of a block of CGs sharing the link reads (up to 16
+ * per block).  stats: nmass entries; iters
  * counts the shared iterations while system i was active plus refinement
  * iterations.  nmass in 1..17, masses finite and >= 0. */
 lqs_status cg_solve_multishift(lqs_ctx *ctx, const lqs_gauge *g, int32_t nmass, const double *masses, const double *b,

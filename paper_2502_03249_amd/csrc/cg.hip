@@ -709,8 +709,10 @@ struct CgRun {
     bool use_graph = false;  // s is a side stream and graphs are on
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    static constexpr int chunk = 4;       // iterations between FP64 groups
-    static constexpr int poll_every = 2;  // chunks between state polls
+    // iterations between FP64 groups (gated launches that return at once unless a
+    // reliable update or the final check is pending) and chunks between state polls
+    static constexpr int chunk = 8;
+    static constexpr int poll_every = 1;
 
     CgRun(Ctx &c, const lqs_problem &p, const lqs_cg_params &pr, lqs_cg_stats *st, hipStream_t str, std::string tg,
           std::chrono::steady_clock::time_point start)
