@@ -270,8 +270,10 @@ lqs_status cg_solve_noalloc(lqs_ctx *ctx, const lqs_problem *prob, const lqs_cg_
  * native even field (nrhs 1); x is a host array of nmass device pointers to
  * FP64 native even fields, overwritten.  Every x_i is finally checked against
  * its own FP64 true residual and refined, when the shared recurrence ended
- * above tol, by a warm-started CG with the same params (mixed precision with
- * reliable updates unless inner_prec is LQS_F64); the masses are refined
+ * above tol, by a warm-started CG with the same params, except that after a
+ * mixed recurrence it runs with FP16-storage inner whenever the gauge holds
+ * the FP16 links of inner_recon (mixed precision with reliable updates unless
+ * inner_prec is LQS_F64); the masses are refined
  * together, one column each of a block of CGs sharing the link reads (up to 16
  * per block).  stats: nmass entries; iters
  * counts the shared iterations while system i was active plus refinement

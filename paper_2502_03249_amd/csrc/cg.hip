@@ -109,14 +109,12 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 // The new search direction r + beta p at site cb, in the accumulation
 // precision (one fused multiply-add per component).
 
-template <int P, int PA>
-__device__ __forceinline__ V3<typename RealOf<PA>::type> direction_at(const char *r, const char *p, int64_t vh, int cb,
+template <int PA>
+__device__ __forceinline__ V3<typename RealOf<PA>::type> direction_of(const V3<typename RealOf<PA>::type> &rv,
+                                                                      const V3<typename RealOf<PA>::type> &pv,
                                                                       typename RealOf<PA>::type beta)
 {
-    typedef typename RealOf<PA>::type TA;
-    const V3<TA> rv = SpinorIO<PA>::load(r, vh, cb);
-    const V3<TA> pv = vcast<TA>(SpinorIO<P>::load(p, vh, cb));
-    V3<TA> o;
+    V3<typename RealOf<PA>::type> o;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         o.c[a].re = fused(beta, pv.c[a].re, rv.c[a].re);
@@ -125,14 +123,24 @@ __device__ __forceinline__ V3<typename RealOf<PA>::type> direction_at(const char
     return o;
 }
 
+template <int P, int PA>
+__device__ __forceinline__ V3<typename RealOf<PA>::type> direction_at(const char *r, const char *p, int64_t vh, int cb,
+                                                                      typename RealOf<PA>::type beta)
+{
+    typedef typename RealOf<PA>::type TA;
+    return direction_of<PA>(SpinorIO<PA>::load(r, vh, cb), vcast<TA>(SpinorIO<P>::load(p, vh, cb)), beta);
+}
+
 // ---------------------------------------------------------------------------
 // 2. q = m^2 p - D_eo t, <p, q>  (output parity even; t odd)
 
 // FP16 storage: left alone the compiler gives the one-vector kernel 120 VGPRs
 // (4 waves per SIMD); held to 6 waves it needs 62, without spills, and the
 // 64^3x16 launch drops from 89.4 to 86.1 us (FP32/FP64 unchanged or slower).
+// Not with LF_PREFETCH, whose words in flight need about 110 VGPRs.
 template <int P, int R, int K, int LF>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(P == F16 ? 6 : 1)))
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu((P == F16 && (LF & LF_PREFETCH) == 0) ? 6 : 1)))
 normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, CgState *st, double *partials,
                                                          int max_blocks, int nrhs, int ngroups, int tmap)
@@ -160,6 +168,9 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
         stage_block_window<P, K>(g, tile * blockDim.x, t + r0 * stride, stride, blk, win, wstride, w0, wlen);
     double dot[K];
     V3<T> acc[K];
+    // LF_PREFETCH: the site's own p is requested with the hop's words
+    typename SpinorIO<P>::Raw praw{};
+    if ((LF & LF_PREFETCH) && act[0]) praw = SpinorIO<P>::load_raw(p + r0 * stride, g.vh, cb);
     if (valid) {
         const Site s = decode(g, cb, 0);
         hop_site<P, R, K, LF>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc, win, wstride, w0, wlen);
@@ -168,7 +179,8 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
     for (int j = 0; j < K; ++j) {
         dot[j] = 0.0;
         if (!act[j]) continue;
-        const V3<T> pv = SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
+        const V3<T> pv = (LF & LF_PREFETCH) ? SpinorIO<P>::decode(praw)
+                                           : SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
         const T m2 = (T)st[r0 + j].m2;
         V3<T> qv;
 #pragma unroll
@@ -199,7 +211,9 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
 // kernel they replace, and FIN_DOT sets alpha instead).  Within this kernel
 // no block reads a state field that another block writes: rho and phase are
 // read, block 0 writes alpha and, on a breakdown (which every block detects
-// by itself), the phase.
+// by itself), the phase.  A thread requests the operands of its first site
+// before the gate and the alpha reduction, whose memory round trips then
+// overlap with them (on small lattices that is its only site).
 
 template <int PA, int PI>
 __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, char *r, const char *p, const char *q,
@@ -210,7 +224,21 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
     typedef typename RealOf<PA>::type T;
     const int rhs = blockIdx.y;
     CgState &S = st[rhs];
-    if (S.phase != CG_RUNNING) return;
+    x += rhs * sa;
+    r += rhs * sa;
+    p += rhs * si;
+    q += rhs * si;
+    const int stride = gridDim.x * blockDim.x;
+    const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cf = c0 < vh ? c0 : vh - 1;  // a valid site for every thread (vh >= 1)
+    const typename SpinorIO<PI>::Raw praw = SpinorIO<PI>::load_raw(p, vh, cf), qraw = SpinorIO<PI>::load_raw(q, vh, cf);
+    const typename SpinorIO<PA>::Raw xraw = SpinorIO<PA>::load_raw(x, vh, cf), rraw = SpinorIO<PA>::load_raw(r, vh, cf);
+    const int phase = S.phase;
+    issue_here(praw);
+    issue_here(qraw);
+    issue_here(xraw);
+    issue_here(rraw);
+    if (phase != CG_RUNNING) return;
     double alpha_d = S.alpha;  // nd_blocks == 0: set by the FIN_DOT finalize
     if (nd_blocks > 0) {
         double acc = 0.0;
@@ -225,16 +253,8 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
         if (lead) S.alpha = alpha_d;
     }
     const T alpha = (T)alpha_d;
-    x += rhs * sa;
-    r += rhs * sa;
-    p += rhs * si;
-    q += rhs * si;
     double local = 0.0;
-    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
-        const V3<T> pv = vcast<T>(SpinorIO<PI>::load(p, vh, cb));
-        const V3<T> qv = vcast<T>(SpinorIO<PI>::load(q, vh, cb));
-        V3<T> xv = SpinorIO<PA>::load(x, vh, cb);
-        V3<T> rv = SpinorIO<PA>::load(r, vh, cb);
+    auto site = [&](int cb, const V3<T> &pv, const V3<T> &qv, V3<T> xv, V3<T> rv) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             xv.c[a].re += alpha * pv.c[a].re;
@@ -245,7 +265,13 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
         }
         SpinorIO<PA>::store(x, vh, cb, xv);
         SpinorIO<PA>::store(r, vh, cb, rv);
-    }
+    };
+    if (c0 < vh)
+        site(c0, vcast<T>(SpinorIO<PI>::decode(praw)), vcast<T>(SpinorIO<PI>::decode(qraw)), SpinorIO<PA>::decode(xraw),
+             SpinorIO<PA>::decode(rraw));
+    for (int cb = c0 + stride; cb < vh; cb += stride)
+        site(cb, vcast<T>(SpinorIO<PI>::load(p, vh, cb)), vcast<T>(SpinorIO<PI>::load(q, vh, cb)),
+             SpinorIO<PA>::load(x, vh, cb), SpinorIO<PA>::load(r, vh, cb));
     const double s = block_sum(local);
     if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
 }
@@ -253,6 +279,8 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
 // ---------------------------------------------------------------------------
 // 4. p = r + beta p
 
+// (as in the update kernel, the first site's operands are requested before
+// the gate)
 template <int PA, int PI>
 __global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char *r, char *p, int64_t sa, int64_t si,
                                                              const CgState *st)
@@ -261,11 +289,22 @@ __global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char 
     typedef typename RealOf<PI>::type TI;
     const int rhs = blockIdx.y;
     const CgState &S = st[rhs];
-    if (S.phase != CG_RUNNING) return;
-    const T beta = (T)S.beta;
     r += rhs * sa;
     p += rhs * si;
-    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x)
+    const int stride = gridDim.x * blockDim.x;
+    const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cf = c0 < vh ? c0 : vh - 1;
+    const typename SpinorIO<PA>::Raw rraw = SpinorIO<PA>::load_raw(r, vh, cf);
+    const typename SpinorIO<PI>::Raw praw = SpinorIO<PI>::load_raw(p, vh, cf);
+    const int phase = S.phase;
+    const T beta = (T)S.beta;
+    issue_here(rraw);
+    issue_here(praw);
+    if (phase != CG_RUNNING) return;
+    if (c0 < vh)
+        SpinorIO<PI>::store(
+            p, vh, c0, vcast<TI>(direction_of<PA>(SpinorIO<PA>::decode(rraw), vcast<T>(SpinorIO<PI>::decode(praw)), beta)));
+    for (int cb = c0 + stride; cb < vh; cb += stride)
         SpinorIO<PI>::store(p, vh, cb, vcast<TI>(direction_at<PI, PA>(r, p, vh, cb, beta)));
 }
 
@@ -386,14 +425,21 @@ __global__ void __launch_bounds__(1024) finalize_kernel(CgState *st, const doubl
                                                        int nblocks, int mode, int gate_mode, int sub)
 {
     const int r = blockIdx.x;
-    CgState &S = st[r];
+    // The state record (into registers) and the partials are requested
+    // together, before the gate decides: one memory round trip instead of
+    // three (gate, partials, then the fields the bookkeeping reads).  The
+    // record is written back whole by thread 0.
+    const double *p = partials + (int64_t)r * max_blocks;
+    const int i0 = threadIdx.x;
+    const double first = p[i0 < nblocks ? i0 : nblocks - 1];  // nblocks >= 1
+    CgState S = st[r];
+    double acc = 0.0;
+    acc += i0 < nblocks ? first : 0.0;
+    for (int i = i0 + blockDim.x; i < nblocks; i += blockDim.x) acc += p[i];
     bool active = true;
     if (mode == FIN_DOT || mode == FIN_UPDATE) active = S.phase == CG_RUNNING;
     else if (mode == FIN_RESID) active = gate_state(S, gate_mode);
     if (!active) return;
-    const double *p = partials + (int64_t)r * max_blocks;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += p[i];
     const double v = block_sum(acc);
     if (threadIdx.x != 0) return;
     if (mode == FIN_DOT) {
@@ -412,6 +458,7 @@ __global__ void __launch_bounds__(1024) finalize_kernel(CgState *st, const doubl
             S.phase = (v == 0.0) ? CG_CONVERGED : (isfinite(v) ? CG_RUNNING : CG_NONFINITE);
         }
     }
+    st[r] = S;
 }
 
 static void launch_finalize(const CgVectors &v, const double *partials, int nblocks, int mode, int gate_mode, int sub,
@@ -457,6 +504,16 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \
     else LQS_ND(4, LF)
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
+    if (sh.rhs_per_thread == 1 && sh.prefetch && !lds) {
+        switch (lf) {
+        case 0: LQS_ND(1, LF_PREFETCH); break;
+        case LF_TEMPORAL: LQS_ND(1, LF_PREFETCH | LF_TEMPORAL); break;
+        case LF_STREAM: LQS_ND(1, LF_PREFETCH | LF_STREAM); break;
+        default: LQS_ND(1, LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
+        }
+        LQS_HIP(hipGetLastError());
+        return;
+    }
     switch (lf) {
     case 0: LQS_ND_LF(0); break;
     case LF_TEMPORAL: LQS_ND_LF(LF_TEMPORAL); break;

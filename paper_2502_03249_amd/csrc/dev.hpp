@@ -160,6 +160,18 @@ template <typename To, typename From> __device__ __forceinline__ To bitcast(cons
 
 template <typename T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 
+// Keeps a load ahead of a branch: its first word becomes an input of an empty
+// asm statement, so the load is issued (and waited for) there instead of being
+// moved past an early return into the code that uses it.  Loads issued just
+// before, such as a gate's state field, then share one memory round trip.
+template <typename Raw> __device__ __forceinline__ void issue_here(const Raw &r)
+{
+    static_assert(sizeof(Raw) >= 4, "a memory word");
+    uint32_t w;
+    __builtin_memcpy(&w, &r, 4);
+    asm volatile("" ::"v"(w));
+}
+
 // Streaming loads for the link arrays.  In one operator application every
 // link word is used by exactly one thread; when the links are far larger than
 // the last-level cache (they are not reused from it across applications
@@ -216,19 +228,32 @@ __device__ __forceinline__ W16 cx_to_h8(const Cx<float> *in)
 // points at word array 0 and vh is the array length.
 template <int P, int R, bool NT = false> struct LinkIO;
 
+// Every format also splits its load into load_raw (the memory words, as
+// fetched) and decode (the arithmetic that turns them into the matrix), with
+// load = decode(load_raw): a kernel may issue the raw loads of several links
+// before decoding any of them and gets the same bits.
 template <int R, bool NT> struct LinkIO<F64, R, NT> {
-    __device__ static __forceinline__ M3<double> load(const void *base, int64_t vh, int cb)
+    static constexpr int rows = (R == 12) ? 2 : 3;
+    struct Raw { double2 d[3 * rows]; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         const double2 *b = (const double2 *)base;
-        M3<double> u;
-        constexpr int rows = (R == 12) ? 2 : 3;
+        Raw r;
 #pragma unroll
-        for (int k = 0; k < 3 * rows; ++k) {
-            double2 d = ld_link<NT>(b + k * vh + cb);
-            u.e[k / 3][k % 3] = {d.x, d.y};
-        }
+        for (int k = 0; k < 3 * rows; ++k) r.d[k] = ld_link<NT>(b + k * vh + cb);
+        return r;
+    }
+    __device__ static __forceinline__ M3<double> decode(const Raw &r)
+    {
+        M3<double> u;
+#pragma unroll
+        for (int k = 0; k < 3 * rows; ++k) u.e[k / 3][k % 3] = {r.d[k].x, r.d[k].y};
         if (R == 12) rebuild_row2(u);
         return u;
+    }
+    __device__ static __forceinline__ M3<double> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<double> &u)
     {
@@ -240,25 +265,32 @@ template <int R, bool NT> struct LinkIO<F64, R, NT> {
 };
 
 template <int R, bool NT> struct LinkIO<F32, R, NT> {
-    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    static constexpr int n4 = (R == 12) ? 3 : 4;
+    struct Raw { float4 d[n4]; float2 t; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         const float4 *b = (const float4 *)base;
+        Raw r;
+#pragma unroll
+        for (int k = 0; k < n4; ++k) r.d[k] = ld_link<NT>(b + k * vh + cb);
+        if (R != 12) r.t = ld_link<NT>((const float2 *)(b + 4 * vh) + cb);
+        return r;
+    }
+    __device__ static __forceinline__ M3<float> decode(const Raw &r)
+    {
         M3<float> u;
-        constexpr int n4 = (R == 12) ? 3 : 4;
 #pragma unroll
         for (int k = 0; k < n4; ++k) {
-            float4 d = ld_link<NT>(b + k * vh + cb);
-            u.e[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
-            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
+            u.e[(2 * k) / 3][(2 * k) % 3] = {r.d[k].x, r.d[k].y};
+            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {r.d[k].z, r.d[k].w};
         }
-        if (R == 12) {
-            rebuild_row2(u);
-        } else {
-            const float2 *t = (const float2 *)(b + 4 * vh);
-            float2 d = ld_link<NT>(t + cb);
-            u.e[2][2] = {d.x, d.y};
-        }
+        if (R == 12) rebuild_row2(u);
+        else u.e[2][2] = {r.t.x, r.t.y};
         return u;
+    }
+    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<float> &u)
     {
@@ -277,22 +309,33 @@ template <int R, bool NT> struct LinkIO<F32, R, NT> {
 };
 
 template <int R, bool NT> struct LinkIO<F16, R, NT> {
-    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    // 12 reals: one 16-byte and one 8-byte word; 18: two 16-byte words and 4 bytes
+    struct Raw { W16 a; W16 b; W8 c; uint32_t t; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         const W16 *b = (const W16 *)base;
+        Raw r;
+        r.a = ld_link<NT>(b + cb);
+        if (R == 12) {
+            r.c = ld_link<NT>((const W8 *)(b + vh) + cb);
+        } else {
+            r.b = ld_link<NT>(b + vh + cb);
+            r.t = ld_link<NT>((const uint32_t *)(b + 2 * vh) + cb);
+        }
+        return r;
+    }
+    __device__ static __forceinline__ M3<float> decode(const Raw &r)
+    {
         M3<float> u;
         Cx<float> e[9];
-        h8_to_cx(ld_link<NT>(b + cb), e);
+        h8_to_cx(r.a, e);
         if (R == 12) {
-            const W8 *t = (const W8 *)(b + vh);
-            W8 w = ld_link<NT>(t + cb);
-            struct H4 { half_t h[4]; } h = bitcast<H4>(w);
+            struct H4 { half_t h[4]; } h = bitcast<H4>(r.c);
             e[4] = {(float)h.h[0], (float)h.h[1]};
             e[5] = {(float)h.h[2], (float)h.h[3]};
         } else {
-            h8_to_cx(ld_link<NT>(b + vh + cb), e + 4);
-            const uint32_t *t = (const uint32_t *)(b + 2 * vh);
-            struct H2 { half_t h[2]; } h = bitcast<H2>(ld_link<NT>(t + cb));
+            h8_to_cx(r.b, e + 4);
+            struct H2 { half_t h[2]; } h = bitcast<H2>(r.t);
             e[8] = {(float)h.h[0], (float)h.h[1]};
         }
         constexpr int n = (R == 12) ? 6 : 9;
@@ -300,6 +343,10 @@ template <int R, bool NT> struct LinkIO<F16, R, NT> {
         for (int k = 0; k < n; ++k) u.e[k / 3][k % 3] = e[k];
         if (R == 12) rebuild_row2(u);
         return u;
+    }
+    __device__ static __forceinline__ M3<float> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const M3<float> &u)
     {
@@ -336,16 +383,25 @@ __host__ __device__ constexpr int64_t spinor_bytes_per_site(int prec)
 template <int P> struct SpinorIO;
 
 template <> struct SpinorIO<F64> {
-    __device__ static __forceinline__ V3<double> load(const void *base, int64_t vh, int cb)
+    struct Raw { double2 d[3]; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         const double2 *b = (const double2 *)base;
+        Raw r;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.d[a] = ldg(b + a * vh + cb);
+        return r;
+    }
+    __device__ static __forceinline__ V3<double> decode(const Raw &r)
+    {
         V3<double> v;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double2 d = ldg(b + a * vh + cb);
-            v.c[a] = {d.x, d.y};
-        }
+        for (int a = 0; a < 3; ++a) v.c[a] = {r.d[a].x, r.d[a].y};
         return v;
+    }
+    __device__ static __forceinline__ V3<double> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<double> &v)
     {
@@ -356,16 +412,23 @@ template <> struct SpinorIO<F64> {
 };
 
 template <> struct SpinorIO<F32> {
-    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    struct Raw { float4 d; float2 e; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         const float4 *b = (const float4 *)base;
-        float4 d = ldg(b + cb);
-        float2 e = ldg((const float2 *)(b + vh) + cb);
+        return {ldg(b + cb), ldg((const float2 *)(b + vh) + cb)};
+    }
+    __device__ static __forceinline__ V3<float> decode(const Raw &r)
+    {
         V3<float> v;
-        v.c[0] = {d.x, d.y};
-        v.c[1] = {d.z, d.w};
-        v.c[2] = {e.x, e.y};
+        v.c[0] = {r.d.x, r.d.y};
+        v.c[1] = {r.d.z, r.d.w};
+        v.c[2] = {r.e.x, r.e.y};
         return v;
+    }
+    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int cb, const V3<float> &v)
     {
@@ -392,15 +455,23 @@ struct alignas(16) SpH {
 };
 
 template <> struct SpinorIO<F16> {
-    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    typedef W16 Raw;
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int cb)
     {
         (void)vh;
-        W16 w = ldg((const W16 *)base + cb);
+        return ldg((const W16 *)base + cb);
+    }
+    __device__ static __forceinline__ V3<float> decode(const Raw &w)
+    {
         SpH q = bitcast<SpH>(w);
         V3<float> v;
 #pragma unroll
         for (int a = 0; a < 3; ++a) v.c[a] = {(float)q.h[2 * a] * q.s, (float)q.h[2 * a + 1] * q.s};
         return v;
+    }
+    __device__ static __forceinline__ V3<float> load(const void *base, int64_t vh, int cb)
+    {
+        return decode(load_raw(base, vh, cb));
     }
     // Scale = max |component| of the site; components stored as binary16 of
     // value / scale (round to nearest even); an all-zero site stores scale 0.

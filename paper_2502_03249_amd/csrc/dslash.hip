@@ -68,6 +68,18 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
     else LQS_HOP(false, LF)
+    if constexpr (K == 1) {
+        if (sh.prefetch && !lds) {
+            switch (lf) {
+            case 0: LQS_HOP_LF(LF_PREFETCH); break;
+            case LF_TEMPORAL: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL); break;
+            case LF_STREAM: LQS_HOP_LF(LF_PREFETCH | LF_STREAM); break;
+            default: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
+            }
+            LQS_HIP(hipGetLastError());
+            return;
+        }
+    }
     switch (lf) {
     case 0: LQS_HOP_LF(0); break;
     case LF_TEMPORAL: LQS_HOP_LF(LF_TEMPORAL); break;
@@ -113,7 +125,10 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 // 128-thread blocks for 2-3 vectors.  Links are streamed when their footprint
 // exceeds STREAM_LINK_BYTES and one group of right-hand sides covers all of
 // them; with several groups the blocks of one site tile reuse the links from
-// L2 (see tile_group) and cached loads win.
+// L2 (see tile_group) and cached loads win.  One vector on a lattice of at
+// most PREFETCH_MAX_SITES sites per parity (a few waves per SIMD) requests
+// all words of a site before the products (LF_PREFETCH).
+static constexpr int64_t PREFETCH_MAX_SITES = (int64_t)1 << 18;
 LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
     LaunchShape sh;
@@ -129,6 +144,7 @@ LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
         sh.rhs_per_thread = 1;
     }
     sh.stream_links = (8 * L.block_bytes >= STREAM_LINK_BYTES && nrhs <= sh.rhs_per_thread) ? 1 : 0;
+    sh.prefetch = (sh.rhs_per_thread == 1 && L.pitch <= PREFETCH_MAX_SITES) ? 1 : 0;
     return sh;
 }
 

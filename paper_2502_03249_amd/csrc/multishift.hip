@@ -15,9 +15,10 @@
 // solve a rational-approximation HMC needs for staggered fermions.
 //
 // One iteration: the base hop and fused normal operator (shared with the
-// plain solver), a finalize for alpha and every zeta, one update kernel that
-// advances all solutions, a finalize for beta, and one kernel that advances
-// all search directions.  The recurrence runs in FP64, or with the search
+// plain solver), a finalize for alpha and every zeta, the base update
+// (x_0, r, |r|^2), a finalize for beta, and one kernel that advances every
+// shifted solution x_i += alpha_i p_i with the p_i it reads anyway and then
+// every search direction (one read of each p_i per iteration, not two).  The recurrence runs in FP64, or with the search
 // directions and the operator in FP32 or FP16 storage and the residual and
 // the solutions in FP32.  In the mixed recurrence the base system takes the
 // reliable updates of the mixed-precision CG: every K iterations, or when
@@ -27,8 +28,8 @@
 // recomputed from it (the shifted residuals stay zeta_i r, which the
 // replacement keeps to the accuracy of the FP64 residual).  Afterwards every
 // mass gets an FP64 true-residual check that also refines it with a
-// warm-started CG (mixed precision when the recurrence was) if the
-// recurrence left it above tol.
+// warm-started CG (mixed precision with FP16 storage when the recurrence was
+// mixed) if the recurrence left it above tol.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -49,6 +50,7 @@ struct ShiftState {
     double alpha, beta;
     int32_t active;                  // still above the target
     int32_t iters;
+    int32_t xupd;                    // alpha was formed this iteration: x_i += alpha p_i is due
 };
 
 struct ShiftPtrs {
@@ -67,6 +69,7 @@ __global__ void __launch_bounds__(1024) ms_finalize_dot(CgState *base, ShiftStat
     for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[i];
     const double pq = block_sum(acc);
     if (threadIdx.x != 0) return;
+    for (int i = 0; i < nshift; ++i) sh[i].xupd = 0;
     if (!isfinite(pq)) {
         S.phase = CG_NONFINITE;
         return;
@@ -84,18 +87,16 @@ __global__ void __launch_bounds__(1024) ms_finalize_dot(CgState *base, ShiftStat
         const double zn = z * zp * a_prev / den;
         T.zeta_next = zn;
         T.alpha = a * zn / z;
+        T.xupd = 1;
     }
     S.alpha = a;
 }
 
-// x_0 += alpha p_0, r -= alpha q, |r|^2; x_i += alpha_i p_i for active shifts.
-// p_0, q and p_i are stored as PI, r and the solutions as PR; the arithmetic
-// is FP64.  (One block grid per system instead of the loop over the shifts
-// measured slower: 0.41 vs 0.37 s for 8 masses on 64^3 x 16 in FP64.)
+// x_0 += alpha p_0, r -= alpha q, |r|^2 of the base.  p_0 and q are stored
+// as PI, r and x_0 as PR; the arithmetic is FP64.
 template <int PI, int PR>
 __global__ void __launch_bounds__(MS_BLOCK) ms_update(int vh, char *x0, char *r, const char *p0, const char *q,
-                                                      const ShiftPtrs *ptr, int nshift, const CgState *base,
-                                                      const ShiftState *sh, double *partials)
+                                                      const CgState *base, double *partials)
 {
     typedef typename RealOf<PR>::type TR;
     if (base->phase != CG_RUNNING) return;
@@ -119,18 +120,6 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_update(int vh, char *x0, char *r,
             local += (double)rs.c[c].re * (double)rs.c[c].re + (double)rs.c[c].im * (double)rs.c[c].im;
         SpinorIO<PR>::store(x0, vh, cb, vcast<TR>(xv));
         SpinorIO<PR>::store(r, vh, cb, rs);
-        for (int i = 0; i < nshift; ++i) {
-            if (!sh[i].active) continue;
-            const double ai = sh[i].alpha;
-            const V3<double> pi = vcast<double>(SpinorIO<PI>::load(ptr->p[i], vh, cb));
-            V3<double> xi = vcast<double>(SpinorIO<PR>::load(ptr->x[i], vh, cb));
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xi.c[c].re += ai * pi.c[c].re;
-                xi.c[c].im += ai * pi.c[c].im;
-            }
-            SpinorIO<PR>::store(ptr->x[i], vh, cb, vcast<TR>(xi));
-        }
     }
     const double s = block_sum(local);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -212,7 +201,24 @@ __global__ void ms_rebeta(const CgState *base, ShiftState *sh, int nshift)
     }
 }
 
-// p_0 = r + beta p_0; p_i = zeta_i r + beta_i p_i for active shifts
+// x_i += alpha_i p_i at site cb, p_i already loaded
+template <int PI, int PR>
+__device__ __forceinline__ void ms_shift_x(const ShiftPtrs *ptr, int i, int vh, int cb, double ai, const V3<double> &pi)
+{
+    typedef typename RealOf<PR>::type TR;
+    V3<double> xi = vcast<double>(SpinorIO<PR>::load(ptr->x[i], vh, cb));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xi.c[c].re += ai * pi.c[c].re;
+        xi.c[c].im += ai * pi.c[c].im;
+    }
+    SpinorIO<PR>::store(ptr->x[i], vh, cb, vcast<TR>(xi));
+}
+
+// x_i += alpha_i p_i where alpha_i was formed this iteration; p_0 = r + beta p_0;
+// p_i = zeta_i r + beta_i p_i for active shifts.  (One block grid per system
+// instead of the loop over the shifts measured slower: 0.41 vs 0.37 s for 8
+// masses on 64^3 x 16 in FP64, as every system re-read the residual.)
 template <int PI, int PR>
 __global__ void __launch_bounds__(MS_BLOCK) ms_pupdate(int vh, const char *r, char *p0, const ShiftPtrs *ptr,
                                                        int nshift, const CgState *base, const ShiftState *sh)
@@ -230,9 +236,12 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_pupdate(int vh, const char *r, ch
         }
         SpinorIO<PI>::store(p0, vh, cb, vcast<TI>(pv));
         for (int i = 0; i < nshift; ++i) {
-            if (!sh[i].active) continue;
-            const double z = sh[i].zeta, bi = sh[i].beta;
+            const bool xu = sh[i].xupd != 0, act = sh[i].active != 0;
+            if (!xu && !act) continue;
             V3<double> pi = vcast<double>(SpinorIO<PI>::load(ptr->p[i], vh, cb));
+            if (xu) ms_shift_x<PI, PR>(ptr, i, vh, cb, sh[i].alpha, pi);
+            if (!act) continue;
+            const double z = sh[i].zeta, bi = sh[i].beta;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 pi.c[c].re = z * rv.c[c].re + bi * pi.c[c].re;
@@ -241,6 +250,23 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_pupdate(int vh, const char *r, ch
             SpinorIO<PI>::store(ptr->p[i], vh, cb, vcast<TI>(pi));
         }
     }
+}
+
+// After the recurrence: the x_i updates of the last iteration, whose p-update
+// was skipped because that iteration ended the recurrence (alpha_i formed,
+// base no longer running).  Nothing to do while the base still runs (the
+// iteration cap of the host loop): its p-update has applied them.
+template <int PI, int PR>
+__global__ void __launch_bounds__(MS_BLOCK) ms_xflush(int vh, const ShiftPtrs *ptr, int nshift, const CgState *base,
+                                                      const ShiftState *sh)
+{
+    if (base->phase == CG_RUNNING) return;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x)
+        for (int i = 0; i < nshift; ++i) {
+            if (!sh[i].xupd) continue;
+            const V3<double> pi = vcast<double>(SpinorIO<PI>::load(ptr->p[i], vh, cb));
+            ms_shift_x<PI, PR>(ptr, i, vh, cb, sh[i].alpha, pi);
+        }
 }
 
 // x_0 = x_i = 0, r = p_0 = p_i = b, |b|^2 (of b in FP64)
@@ -393,8 +419,8 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
             hipLaunchKernelGGL(ms_finalize_dot, dim3(1), dim3(1024), 0, s, v.state, dsh, nshift,
                                (const double *)v.partials, nd_blocks);
             LQS_MS_PREC(hipLaunchKernelGGL((ms_update<P_I, P_R>), dim3(blocks), dim3(MS_BLOCK), 0, s, vh, xr[base],
-                                           (char *)v.r, (const char *)v.p, (const char *)v.q, (const ShiftPtrs *)dp,
-                                           nshift, (const CgState *)v.state, (const ShiftState *)dsh, v.partials));
+                                           (char *)v.r, (const char *)v.p, (const char *)v.q,
+                                           (const CgState *)v.state, v.partials));
             hipLaunchKernelGGL(ms_finalize_update, dim3(1), dim3(1024), 0, s, v.state, dsh, nshift,
                                (const double *)v.partials, blocks);
             if (mixed && (i & 3) == 3) {
@@ -414,6 +440,12 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
         LQS_HIP(hipStreamSynchronize(s));
         if (hs.phase != CG_RUNNING || enqueued > cap) break;
     }
+    if (nshift) {
+        LQS_MS_PREC(hipLaunchKernelGGL((ms_xflush<P_I, P_R>), dim3(blocks), dim3(MS_BLOCK), 0, s, vh,
+                                       (const ShiftPtrs *)dp, nshift, (const CgState *)v.state,
+                                       (const ShiftState *)dsh));
+    }
+    LQS_HIP(hipGetLastError());
     if (nshift) LQS_HIP(hipMemcpyAsync(hsh.data(), dsh, sizeof(ShiftState) * nshift, hipMemcpyDeviceToHost, s));
     LQS_HIP(hipStreamSynchronize(s));
 
@@ -432,6 +464,12 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     lqs_cg_params rp = prm;
     rp.use_x0 = 1;
     rp.persistent = 0;
+    // A refinement starts close to its solution (about 1e-7 relative after an
+    // FP32 recurrence), where FP16 storage takes the same iterations as FP32 and
+    // each is cheaper: after a mixed recurrence the refinement runs with FP16
+    // storage when the gauge holds that format (measured, 64^3 x 16, 8 masses,
+    // FP32 recurrence: 41 refinement iterations either way, 57 vs 71 ms).
+    if (mixed && gauge.fmt[F16][v.recon == 12 ? 1 : 0]) rp.inner_prec = F16;
     const int64_t f64 = field_bytes(g, F64, 1);
     const int per_block = std::min(nmass, 16);
     char *xb = (char *)ctx.workspace("ms.xblock", f64 * per_block);

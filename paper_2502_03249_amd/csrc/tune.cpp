@@ -45,29 +45,32 @@ Tuner::Tuner(const char *p)
 }
 
 // On a hit the stored fields replace those of `out`; an entry without the
-// third, fourth or fifth field keeps out.stream_links, out.xcd_slab or out.lds.
+// third, fourth, fifth or sixth field keeps out.stream_links, out.xcd_slab,
+// out.lds or out.prefetch.
 bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) const
 {
     auto it = cache.find(key);
     if (it == cache.end()) return false;
-    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab, ld = out.lds;
-    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld);
+    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab, ld = out.lds, pf = out.prefetch;
+    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld, &pf);
     if (n < 2) return false;
     if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1) ||
-        !(sl >= -1 && sl <= 2) || !(ld == 0 || ld == 1))
+        !(sl >= -1 && sl <= 2) || !(ld == 0 || ld == 1) || !(pf == 0 || pf == 1))
         return false;
     out.block = b;
     out.rhs_per_thread = k;
     out.stream_links = st;
     out.xcd_slab = sl;
     out.lds = ld;
+    out.prefetch = pf;
     return true;
 }
 
 void Tuner::store(const std::string &key, const LaunchShape &v)
 {
     cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread) + "," +
-                 std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab) + "," + std::to_string(v.lds);
+                 std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab) + "," + std::to_string(v.lds) +
+                 "," + std::to_string(v.prefetch);
 }
 
 void Tuner::save() const
@@ -101,7 +104,14 @@ static std::vector<LaunchShape> candidates(int nrhs)
     for (int k : {1, 2, 4}) {
         if (k > nrhs) break;
         for (int b : {64, 128, 256, 512})
-            for (int st : {0, 1}) c.push_back({b, k, st});
+            for (int st : {0, 1}) {
+                c.push_back({b, k, st});
+                if (k == 1) {
+                    LaunchShape pf{b, k, st};
+                    pf.prefetch = 1;
+                    c.push_back(pf);
+                }
+            }
     }
     return c;
 }
@@ -194,6 +204,7 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // then the kernel with its x/y neighbours staged through LDS, where the window fits
     LaunchShape staged = best_shape;
     staged.lds = 1;
+    staged.prefetch = 0;
     if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged) > 0) consider(staged);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -31,6 +31,9 @@ def test_multishift_matches_separate_solves(ctx, dims, kind, masses):
     base_iters = max(s["iters"] for s in st)
     for m, x, s in zip(masses, xs, st):
         assert s["status"] == 0, s
+        # the FP64 recurrence alone brings every mass to tol: no refinement CG ran (a lost
+        # x_i += alpha_i p_i anywhere in the recurrence would leave that mass above tol)
+        assert s["restarts"] == 0, s
         xv = lex_of(ctx, x)
         assert oracle.true_residual(dims, U, m, b, xv) <= 1e-10
         xo, _, _, _ = oracle.cg(dims, U, m, b, tol=1e-11)

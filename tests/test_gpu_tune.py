@@ -42,8 +42,9 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
     assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
     for v in entries.values():
-        blk, k, st, sl, ld = (int(t) for t in v.split(","))
-        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1) and ld in (0, 1)
+        blk, k, st, sl, ld, pf = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1, 2)
+        assert ld in (0, 1) and pf in (0, 1) and (pf == 0 or (k == 1 and ld == 0))
 
     # the persistent multi-lattice solve tunes its resident blocks per compute unit
     tuned = lqs.Context(0, tune_cache=cache, tuning=True)
@@ -312,3 +313,76 @@ def test_lds_staged_hop_in_cg_two_columns(tmp_path, prec, recon):
         runs.append((x, [(s_["iters"], s_["reliable_updates"]) for s_ in st]))
         ctx.close()
     assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+
+
+def _arch():
+    return torch.cuda.get_device_properties(0).gcnArchName
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 16), (4, 6, 8, 10)])
+def test_prefetch_hop_is_bit_identical(tmp_path, dims):
+    """The one-vector hop that requests all words of a site before its products (LF_PREFETCH)
+    gives the bits of the plain hop in all six link formats, with cached and streaming link
+    loads, and in temporal gauge (unit t-links by site index); both agree with the oracle."""
+    U = synth.gauge(dims, "haar", seed=97)
+    ctx0 = lqs.Context(0)
+    Uf = lqs.gauge_fix_temporal(ctx0, dims, torch.from_numpy(U).to("cuda"))[0].cpu().numpy()
+    ctx0.close()
+    src = synth.source(dims, 1, seed=970)
+    tag = "x".join(str(d) for d in dims)
+    cache = str(tmp_path / "tune.json")
+    fmts = [(pr, rc) for pr in (lqs.F64, lqs.F32, lqs.F16) for rc in (18, 12)]
+    bound = {lqs.F64: 1e-12, lqs.F32: 2e-6, lqs.F16: 4e-3}
+    for st in (0, 1):
+        outs = []
+        for pf in (0, 1):
+            entries = {}
+            for kern in ("hop", "hop_tg"):
+                for pr, rc in fmts:
+                    entries["|".join([_arch(), kern, tag, "p%d" % pr, "r%d" % rc, "n1"])] = "64,1,%d,-1,0,%d" % (st, pf)
+            with open(cache, "w") as f:
+                json.dump(entries, f)
+            ctx = lqs.Context(0, tune_cache=cache)
+            g = gauge(ctx, dims, U)
+            gt = lqs.Gauge(ctx, dims, torch.from_numpy(Uf).to("cuda"), lqs.FMT_ALL | lqs.TEMPORAL_GAUGE)
+            y = [lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, src, 1, pr), recon=rc)) for pr, rc in fmts]
+            yt = [lex_of(ctx, lqs.dslash_apply(ctx, gt, field(ctx, dims, src, 1, pr), recon=12))
+                  for pr in (lqs.F64, lqs.F32, lqs.F16)]
+            outs.append((y, yt))
+            ctx.close()
+            assert json.load(open(cache)) == entries
+        for a, b in zip(outs[0][0] + outs[0][1], outs[1][0] + outs[1][1]):
+            assert np.array_equal(a, b)
+        want, want_t = oracle.dslash(dims, U, src, 0), oracle.dslash(dims, Uf, src, 0)
+        for (pr, rc), y in zip(fmts, outs[1][0]):
+            assert rel(y, want) <= bound[pr], (pr, rc)
+        for pr, y in zip((lqs.F64, lqs.F32, lqs.F16), outs[1][1]):
+            assert rel(y, want_t) <= bound[pr], pr
+
+
+@pytest.mark.parametrize("prec,recon", [(lqs.F16, 12), (lqs.F32, 12), (lqs.F64, 18)])
+def test_prefetch_in_cg(tmp_path, prec, recon):
+    """A CG whose hop and fused normal kernel prefetch (LF_PREFETCH) gives the plain solve's bits,
+    iteration count and reliable updates."""
+    dims, mass = (8, 8, 8, 16), 0.05
+    U = synth.gauge(dims, "smooth", seed=98, eps=0.3)
+    b = synth.source(dims, 0, seed=980)
+    cache = str(tmp_path / "tune.json")
+    runs = []
+    for pf in (0, 1):
+        entries = {"|".join([_arch(), kern, "8x8x8x16", "p%d" % pr, "r%d" % rc, "n1"]): "256,1,0,-1,0,%d" % pf
+                   for kern in ("hop", "normal_dot") for pr in (lqs.F64, prec) for rc in (18, recon)}
+        with open(cache, "w") as f:
+            json.dump(entries, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        g = gauge(ctx, dims, U)
+        bf = field(ctx, dims, b, 0)
+        xf = bf.like().zero_()
+        st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=prec, inner_recon=recon,
+                          reliable_interval=100)
+        x = lex_of(ctx, xf)
+        assert st[0]["status"] == 0
+        assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
+        runs.append((x, st[0]["iters"], st[0]["reliable_updates"]))
+        ctx.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1:] == runs[1][1:]
