@@ -356,6 +356,7 @@ def main():
         "cg": {"mixed_s": round(mixed_s, 5), "mixed_eager_profiled_s": round(eager_s, 5),
                "mixed_iters": stats[-1]["iters"],
                "mixed_reliable_updates": stats[-1]["reliable_updates"],
+               "mixed_gflops": round(stats[-1]["gflops"], 1), "mixed_gbytes_per_s": round(stats[-1]["gbytes_per_s"], 1),
                "mixed_true_res": stats[-1]["true_rel_residual"], "mixed_x_rel_err_vs_fp64": err_mixed,
                "x_rel_err_vs_oracle": oracle_err,
                "all_converged": ok,

@@ -223,6 +223,16 @@ typedef struct {
                                   from the first to the last kernel of the problem (stream
                                   events); 0 where not measured (cg_solve_noalloc,
                                   cg_solve_multishift)                                      */
+    double gflops;             /* 1140 flop per even site and iteration (the two hops of M,
+                                  570 each, Sec. 4.3) x iters / time, in GFLOP/s; time is
+                                  device_seconds, or seconds where that is 0.  0 from
+                                  cg_solve_multishift (its iterations differ in work)        */
+    double gbytes_per_s;       /* algorithmic bytes of an iteration x iters / time, GB/s:
+                                  per hop the links once (8 per site, 6 + 2/Nt in temporal
+                                  gauge, shared by the right-hand sides of one problem) and
+                                  each colour vector once per kernel of the iteration (hop,
+                                  normal operator, update, p-update); reliable updates and
+                                  the final check are not counted                            */
 } lqs_cg_stats;
 
 /* Solve nprob systems.  stats receives one entry per (problem, right-hand

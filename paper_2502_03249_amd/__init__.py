@@ -52,7 +52,7 @@ class LqsCgParams(ctypes.Structure):
 class LqsCgStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("device_seconds", ctypes.c_double)]
+                ("device_seconds", ctypes.c_double), ("gflops", ctypes.c_double), ("gbytes_per_s", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -478,6 +478,24 @@ static int blas_blocks(int64_t vh)
     return (int)(b < 1024 ? b : 1024);
 }
 
+void cg_fill_rates(lqs_cg_stats &o, const Gauge &gauge, int prec, int recon, int nrhs)
+{
+    const double t = o.device_seconds > 0 ? o.device_seconds : o.seconds;
+    if (!(t > 0) || o.iters <= 0) {
+        o.gflops = o.gbytes_per_s = 0.0;
+        return;
+    }
+    const double real = prec == F64 ? 8 : prec == F32 ? 4 : 2;
+    const double lps = gauge.temporal ? 6.0 + 2.0 / gauge.g.n[3] : 8.0;
+    const double L = lps * real * recon / (nrhs > 0 ? nrhs : 1);
+    const double sv = (double)spinor_bytes_per_site(prec), a = (double)spinor_bytes_per_site(prec == F64 ? F64 : F32);
+    // t = D_oe p; q = m^2 p - D_eo t; x, r updated from p, q; p = r + beta p
+    const double bytes = (L + 2 * sv) + (L + 3 * sv) + (4 * a + 2 * sv) + (a + 2 * sv);
+    const double n = (double)gauge.vh * o.iters;
+    o.gflops = 1140.0 * n / t * 1e-9;
+    o.gbytes_per_s = bytes * n / t * 1e-9;
+}
+
 int cg_partials_needed(const Gauge &gauge, int nrhs)
 {
     (void)nrhs;
@@ -958,6 +976,7 @@ struct CgRun {
             o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
             o.seconds = secs;
             o.device_seconds = 1e-3 * dev_ms;
+            cg_fill_rates(o, gauge(), v.prec, v.recon, nrhs);
             switch (S.phase) {
             case CG_CONVERGED: o.status = LQS_OK; break;
             case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;

@@ -214,6 +214,10 @@ struct CgVectors {
 void cg_init(Ctx &ctx, const Gauge &gauge, CgVectors &v, bool use_x0, hipStream_t s);
 void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, bool with_reliable);
 int cg_partials_needed(const Gauge &gauge, int nrhs);
+// gflops and gbytes_per_s of one right-hand side's stats from its iterations
+// and times (inner precision and link format of the iteration; nrhs
+// right-hand sides share the link reads)
+void cg_fill_rates(lqs_cg_stats &o, const Gauge &gauge, int prec, int recon, int nrhs);
 
 // force.hip
 void launch_force(const Geom &g, LinkRef links64, const double *X, const double *Y, const double *psx,

@@ -497,6 +497,7 @@ void multishift_solve(Ctx &ctx, const Gauge &gauge, int nmass, const double *mas
     for (int i = 0; i < nmass; ++i) {
         stats[i].seconds = secs;
         stats[i].device_seconds = 0.0;
+        stats[i].gflops = stats[i].gbytes_per_s = 0.0;
     }
 }
 

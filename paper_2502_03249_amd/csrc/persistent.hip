@@ -564,6 +564,7 @@ void persistent_solve(Ctx &ctx, const std::vector<PersistentProblem> &probs, con
         o.true_rel_residual = S.b2 > 0 ? std::sqrt(S.true_r2 / S.b2) : 0.0;
         o.seconds = secs;
         o.device_seconds = clk_khz > 0 ? (double)(hclk[2 * l + 1] - hclk[2 * l]) / (1e3 * clk_khz) : 0.0;
+        cg_fill_rates(o, *probs[l].gauge, prec, recon, 1);
         switch (S.phase) {
         case CG_CONVERGED: o.status = LQS_OK; break;
         case CG_BREAKDOWN: o.status = LQS_EBREAKDOWN; break;

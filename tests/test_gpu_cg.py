@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import synth
+from paper_2502_03249_amd import model
 from gpu_util import field, gauge, lex_of, rel
 
 pytestmark = pytest.mark.gpu
@@ -72,6 +73,13 @@ def test_cg_mixed_precision_reaches_fp64_residual(ctx, prec, recon):
     assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
     xo, _, _, _ = oracle.cg(dims, U, mass, b)
     assert rel(x, xo) <= (mass ** 2 + 64) / mass ** 2 * 1e-10
+    # reported rates: 1140 flop and the model's algorithmic bytes per even site and iteration
+    s0 = st[0]
+    n = np.prod(dims) // 2 * s0["iters"]
+    assert s0["device_seconds"] > 0
+    assert s0["gflops"] == pytest.approx(1140 * n / s0["device_seconds"] * 1e-9, rel=1e-12)
+    want_b = model.cg_iteration_bytes(prec, lqs.F32, recon) * n / s0["device_seconds"] * 1e-9
+    assert s0["gbytes_per_s"] == pytest.approx(want_b, rel=1e-12)
 
 
 @pytest.mark.parametrize("prec", [lqs.F64, lqs.F32, lqs.F16])
