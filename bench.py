@@ -854,7 +854,8 @@ def run_suite(a):
         nsel = min([ns for ns in scan if abs(scan[ns]) < 1.0] or [160])
         emit({"suite": "hmc_24x4_step_scan", "dH_by_nsteps": scan, "chosen_nsteps": nsel})
         rng = np.random.default_rng(3100)
-        for inner, recon, ftol in (("f64", 18, 0.0), ("f32", 12, 0.0), ("f16", 12, 0.0), ("f16", 12, 1e-7)):
+        for inner, recon, ftol in (("f64", 18, 0.0), ("f32", 12, 0.0), ("f16", 12, 0.0), ("f32", 12, 1e-7),
+                                   ("f16", 12, 1e-7)):
             res = []
             for k in range(2):
                 U0 = Ud.clone()
