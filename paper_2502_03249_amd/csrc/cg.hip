@@ -168,9 +168,10 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
         stage_block_window<P, K>(g, tile * blockDim.x, t + r0 * stride, stride, blk, win, wstride, w0, wlen);
     double dot[K];
     V3<T> acc[K];
-    // LF_PREFETCH: the site's own p is requested with the hop's words
+    // LF_PREFETCH with one vector: the site's own p is requested with the hop's words
+    constexpr bool PF1 = (LF & LF_PREFETCH) != 0 && K == 1;
     typename SpinorIO<P>::Raw praw{};
-    if ((LF & LF_PREFETCH) && act[0]) praw = SpinorIO<P>::load_raw(p + r0 * stride, g.vh, cb);
+    if (PF1 && act[0]) praw = SpinorIO<P>::load_raw(p + r0 * stride, g.vh, cb);
     if (valid) {
         const Site s = decode(g, cb, 0);
         hop_site<P, R, K, LF>(g, L, 0, s, cb, t + r0 * stride, stride, act, acc, win, wstride, w0, wlen);
@@ -179,8 +180,7 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
     for (int j = 0; j < K; ++j) {
         dot[j] = 0.0;
         if (!act[j]) continue;
-        const V3<T> pv = (LF & LF_PREFETCH) ? SpinorIO<P>::decode(praw)
-                                           : SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
+        const V3<T> pv = PF1 ? SpinorIO<P>::decode(praw) : SpinorIO<P>::load(p + (r0 + j) * stride, g.vh, cb);
         const T m2 = (T)st[r0 + j].m2;
         V3<T> qv;
 #pragma unroll
@@ -522,12 +522,12 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     else if (sh.rhs_per_thread == 2) LQS_ND(2, LF);                                                              \
     else LQS_ND(4, LF)
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
-    if (sh.rhs_per_thread == 1 && sh.prefetch && !lds) {
+    if (sh.prefetch && !lds) {
         switch (lf) {
-        case 0: LQS_ND(1, LF_PREFETCH); break;
-        case LF_TEMPORAL: LQS_ND(1, LF_PREFETCH | LF_TEMPORAL); break;
-        case LF_STREAM: LQS_ND(1, LF_PREFETCH | LF_STREAM); break;
-        default: LQS_ND(1, LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
+        case 0: LQS_ND_LF(LF_PREFETCH); break;
+        case LF_TEMPORAL: LQS_ND_LF(LF_PREFETCH | LF_TEMPORAL); break;
+        case LF_STREAM: LQS_ND_LF(LF_PREFETCH | LF_STREAM); break;
+        default: LQS_ND_LF(LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
         }
         LQS_HIP(hipGetLastError());
         return;

@@ -68,17 +68,15 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
 #define LQS_HOP_LF(LF)                                                                                           \
     if (dagger) LQS_HOP(true, LF);                                                                                \
     else LQS_HOP(false, LF)
-    if constexpr (K == 1) {
-        if (sh.prefetch && !lds) {
-            switch (lf) {
-            case 0: LQS_HOP_LF(LF_PREFETCH); break;
-            case LF_TEMPORAL: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL); break;
-            case LF_STREAM: LQS_HOP_LF(LF_PREFETCH | LF_STREAM); break;
-            default: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
-            }
-            LQS_HIP(hipGetLastError());
-            return;
+    if (sh.prefetch && !lds) {
+        switch (lf) {
+        case 0: LQS_HOP_LF(LF_PREFETCH); break;
+        case LF_TEMPORAL: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL); break;
+        case LF_STREAM: LQS_HOP_LF(LF_PREFETCH | LF_STREAM); break;
+        default: LQS_HOP_LF(LF_PREFETCH | LF_TEMPORAL | LF_STREAM); break;
         }
+        LQS_HIP(hipGetLastError());
+        return;
     }
     switch (lf) {
     case 0: LQS_HOP_LF(0); break;
@@ -119,23 +117,25 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 }
 
 // Default shapes from measured sweeps on 32^4, 32^3x8 and 64^3x16: from 4
-// vectors on, 4 right-hand sides per thread in 128-thread blocks with the
-// time-inner block -> tile map (at 64^3x16 with 16 vectors 6-17 % faster than
-// 64-thread blocks in lexicographic order, equal on 32^4); 2 per thread in
-// 128-thread blocks for 2-3 vectors.  Links are streamed when their footprint
-// exceeds STREAM_LINK_BYTES and one group of right-hand sides covers all of
-// them; with several groups the blocks of one site tile reuse the links from
-// L2 (see tile_group) and cached loads win.  One vector on a lattice of at
-// most PREFETCH_MAX_SITES sites per parity (a few waves per SIMD) requests
-// all words of a site before the products (LF_PREFETCH).
+// vectors on, 4 right-hand sides per thread in 256-thread blocks with the
+// time-inner block -> tile map and prefetched words (steady state, 64^3x16,
+// 4 vectors: FP16 12-real 154 against 197 us without prefetch, FP32 250
+// against 331, FP64 12-real 501 against 623; 16 vectors 10-20 % faster on
+// 32^4 and 64^3x16); 2 per thread in 128-thread blocks for 2-3 vectors.
+// Links are streamed when their footprint exceeds STREAM_LINK_BYTES and one
+// group of right-hand sides covers all of them; with several groups the
+// blocks of one site tile reuse the links from L2 (see tile_group) and cached
+// loads win.  One vector on a lattice of at most PREFETCH_MAX_SITES sites per
+// parity (a few waves per SIMD) is prefetched too.
 static constexpr int64_t PREFETCH_MAX_SITES = (int64_t)1 << 18;
 LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
     LaunchShape sh;
     if (nrhs >= 4) {
-        sh.block = 128;
+        sh.block = 256;
         sh.rhs_per_thread = 4;
         sh.xcd_slab = 2;
+        sh.prefetch = 1;
     } else if (nrhs >= 2) {
         sh.block = 128;
         sh.rhs_per_thread = 2;
@@ -144,7 +144,7 @@ LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
         sh.rhs_per_thread = 1;
     }
     sh.stream_links = (8 * L.block_bytes >= STREAM_LINK_BYTES && nrhs <= sh.rhs_per_thread) ? 1 : 0;
-    sh.prefetch = (sh.rhs_per_thread == 1 && L.pitch <= PREFETCH_MAX_SITES) ? 1 : 0;
+    if (sh.rhs_per_thread == 1) sh.prefetch = L.pitch <= PREFETCH_MAX_SITES ? 1 : 0;
     return sh;
 }
 

@@ -12,12 +12,11 @@ namespace lqs {
 // LF_TEMPORAL, the links are in temporal gauge (U_t = 1 off the last time
 // slice) and those t-links are not read from the link arrays (without it every
 // link is read, also correct for temporal-gauge links, just slower);
-// LF_STREAM, link words are fetched with streaming loads; LF_PREFETCH (one
-// right-hand side, no LDS window), the memory words of all eight directions
-// (FP16 and FP32 storage; four at a time in FP64) are requested before any is
-// used.  Inactive right-hand sides are skipped and keep acc = 0.  `in` points at right-hand side 0 of
-// the input field (parity 1 - parity); consecutive sides are in_stride bytes
-// apart.
+// LF_STREAM, link words are fetched with streaming loads; LF_PREFETCH (no
+// LDS window), the memory words of a group of directions are all requested
+// before any is used.  Inactive right-hand sides are skipped and keep
+// acc = 0.  `in` points at right-hand side 0 of the input field (parity
+// 1 - parity); consecutive sides are in_stride bytes apart.
 enum { LF_TEMPORAL = 1, LF_STREAM = 2, LF_LDS = 4, LF_PREFETCH = 8 };
 
 // Block -> (site tile, right-hand-side group).  Consecutive block indices go
@@ -159,21 +158,22 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = vzero<T>();
     if constexpr ((LF & LF_PREFETCH) != 0) {
-        // The compiler otherwise keeps two or three loads in flight per wave
-        // (it holds registers down for occupancy), so a hop costs eight
-        // dependent memory round trips: with few waves per SIMD (lattices up
-        // to about 24^4) nothing hides them.  Here a group of directions has
-        // all its words requested, a scheduling barrier keeps the decoding
-        // below them, and the products accumulate in the order of the loop
-        // below (same bits).
-        static_assert(K == 1 && (LF & LF_LDS) == 0, "prefetch: one right-hand side, no LDS window");
+        // The compiler otherwise keeps a few loads in flight per wave (it
+        // holds registers down for occupancy) and waits for each direction's
+        // words before it asks for the next.  Here a group of directions has
+        // all its words requested (the links and every right-hand side's
+        // neighbour), a scheduling barrier keeps the decoding below them, and
+        // the products accumulate in the order of the loop below (same bits).
+        // Inactive right-hand sides load side 0's words and drop them, so that
+        // no load sits behind a branch.  Groups: all eight directions for one
+        // FP16/FP32 vector, four for two, two for four; FP64 four, then two.
+        static_assert((LF & LF_LDS) == 0, "prefetch: no LDS window");
         typedef LinkIO<P, R, NT> LIO;
-        constexpr int GRP = P == F64 ? 4 : 8;
-        if (!active[0]) return;
+        constexpr int GRP = P == F64 ? (K == 1 ? 4 : 2) : (K == 1 ? 8 : K == 2 ? 4 : 2);
 #pragma unroll
         for (int d0 = 0; d0 < 8; d0 += GRP) {
             typename LIO::Raw lr[GRP];
-            typename SpinorIO<P>::Raw vr[GRP];
+            typename SpinorIO<P>::Raw vr[GRP][K];
 #pragma unroll
             for (int k = 0; k < GRP; ++k) {
                 const int d = d0 + k, mu = d >> 1;
@@ -181,16 +181,23 @@ __device__ __forceinline__ void hop_site(const Geom &g, const LinkRef &L, int pa
                 const bool unit = TG && mu == 3 && (s.tunit & (fwd ? 1u : 2u));
                 const int at = unit ? g.vh : (fwd ? cb : s.bwd[mu]);
                 lr[k] = LIO::load_raw(lb + (2 * mu + (fwd ? parity : 1 - parity)) * L.block_bytes, L.pitch, at);
-                vr[k] = SpinorIO<P>::load_raw(in, g.vh, fwd ? s.fwd[mu] : s.bwd[mu]);
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    vr[k][j] = SpinorIO<P>::load_raw(in + (active[j] ? j : 0) * in_stride, g.vh,
+                                                     fwd ? s.fwd[mu] : s.bwd[mu]);
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int k = 0; k < GRP; ++k) {
                 const int d = d0 + k, mu = d >> 1;
                 const M3<T> u = LIO::decode(lr[k]);
-                const V3<T> v = SpinorIO<P>::decode(vr[k]);
-                if ((d & 1) == 0) accum(acc[0], mv(u, v), (s.negf >> mu) & 1);
-                else accum(acc[0], mdv(u, v), !((s.negb >> mu) & 1));
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    if (!active[j]) continue;
+                    const V3<T> v = SpinorIO<P>::decode(vr[k][j]);
+                    if ((d & 1) == 0) accum(acc[j], mv(u, v), (s.negf >> mu) & 1);
+                    else accum(acc[j], mdv(u, v), !((s.negb >> mu) & 1));
+                }
             }
         }
         return;

@@ -180,8 +180,8 @@ struct LaunchShape {
     int stream_links = 0;  // 1: link words fetched with streaming (nontemporal) loads
     int xcd_slab = -1;     // block -> tile map: 0 round robin, 1 one slab per XCD, -1 by lattice shape
     int lds = 0;           // 1: x and y neighbours from an LDS window of the block's input sites
-    int prefetch = 0;      // 1 (one right-hand side per thread, no LDS): all link and neighbour
-                           // words of a site requested before the products (LF_PREFETCH)
+    int prefetch = 0;      // 1 (no LDS window): the words of a group of directions requested
+                           // before their products (LF_PREFETCH)
 };
 // Link footprint from which the hop streams its links by default: beyond
 // about three quarters of the 256 MB last-level cache (MALL) the links of one

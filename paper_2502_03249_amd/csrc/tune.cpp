@@ -2,12 +2,12 @@
 //
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
-// thread x cached or streaming link loads, then the other block -> XCD map
-// and LDS staging of the input window for the best of these)
+// thread x cached or streaming link loads x prefetched words, then the other
+// block -> XCD maps and LDS staging of the input window for the best of these)
 // with HIP events on the caller's stream, keeps the one with the lowest
 // median time, and stores it in a flat JSON object
-// {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds", ...} that later
-// runs load.  Tuning runs
+// {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds,prefetch", ...} that
+// later runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
 #include <cstring>
@@ -106,11 +106,9 @@ static std::vector<LaunchShape> candidates(int nrhs)
         for (int b : {64, 128, 256, 512})
             for (int st : {0, 1}) {
                 c.push_back({b, k, st});
-                if (k == 1) {
-                    LaunchShape pf{b, k, st};
-                    pf.prefetch = 1;
-                    c.push_back(pf);
-                }
+                LaunchShape pf{b, k, st};
+                pf.prefetch = 1;
+                c.push_back(pf);
             }
     }
     return c;
