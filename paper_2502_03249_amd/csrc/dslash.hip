@@ -121,12 +121,15 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 // time-inner block -> tile map and prefetched words (steady state, 64^3x16,
 // 4 vectors: FP16 12-real 154 against 197 us without prefetch, FP32 250
 // against 331, FP64 12-real 501 against 623; 16 vectors 10-20 % faster on
-// 32^4 and 64^3x16); 2 per thread in 128-thread blocks for 2-3 vectors.
-// Links are streamed when their footprint exceeds STREAM_LINK_BYTES and one
-// group of right-hand sides covers all of them; with several groups the
-// blocks of one site tile reuse the links from L2 (see tile_group) and cached
-// loads win.  One vector on a lattice of at most PREFETCH_MAX_SITES sites per
-// parity (a few waves per SIMD) is prefetched too.
+// 32^4 and 64^3x16); 2 per thread in 128-thread blocks for 2-3 vectors, also
+// prefetched (3 vectors at 64^3x16: FP32 12-real 252 against 336 us, FP64
+// 18-real 688 against 903 us; 2 vectors 0-8 % faster).  Links are streamed
+// when their footprint exceeds STREAM_LINK_BYTES and one group of right-hand
+// sides covers all of them; with several groups the blocks of one site tile
+// reuse the links from L2 (see tile_group) and cached loads win.  One vector
+// on a lattice of at most PREFETCH_MAX_SITES sites per parity (a few waves per
+// SIMD) is prefetched too; on larger ones prefetch is within -7 .. +5 % and
+// left to the tuner.
 static constexpr int64_t PREFETCH_MAX_SITES = (int64_t)1 << 18;
 LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
 {
@@ -139,6 +142,7 @@ LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
     } else if (nrhs >= 2) {
         sh.block = 128;
         sh.rhs_per_thread = 2;
+        sh.prefetch = 1;
     } else {
         sh.block = 256;
         sh.rhs_per_thread = 1;
