@@ -10,6 +10,7 @@
 // later runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -159,14 +160,17 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LQS_HIP(hipEventCreate(&e0));
     LQS_HIP(hipEventCreate(&e1));
     const LinkRef L = gauge.ref(prec, recon);
+    auto launch_once = [&](const LaunchShape &c) {
+        if (is_dot) launch_normal_dot_shape(gauge, v, c, s);
+        else launch_hop_gated(g, L, prec, recon, 0, 1, nrhs, in, out, nullptr, 0, c, s);
+    };
     auto time_shape = [&](const LaunchShape &c) {
         std::vector<float> t;
         for (int rep = 0; rep < 7; ++rep) {
             if (is_dot)
                 LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
             LQS_HIP(hipEventRecord(e0, s));
-            if (is_dot) launch_normal_dot_shape(gauge, v, c, s);
-            else launch_hop_gated(g, L, prec, recon, 0, 1, nrhs, in, out, nullptr, 0, c, s);
+            launch_once(c);
             LQS_HIP(hipEventRecord(e1, s));
             LQS_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -182,6 +186,23 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // this way made the 64^3 x 16 solve 1 % slower than the default).
     constexpr float MARGIN = 0.98f;
     LaunchShape best_shape = default_hop_shape(L, nrhs);
+    // After an idle spell the first launches run slower for several
+    // milliseconds; the default shape, timed first, would be measured cold
+    // against candidates timed warm.  Run it back to back for about 20 ms
+    // first (the normal kernel's gate is set to running for every launch).
+    {
+        const auto w0 = std::chrono::steady_clock::now();
+        for (int i = 0; i < 500; ++i) {
+            if (is_dot)
+                LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
+            launch_once(best_shape);
+            if ((i & 3) == 3) {
+                LQS_HIP(hipStreamSynchronize(s));
+                if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 0.02) break;
+            }
+        }
+        LQS_HIP(hipStreamSynchronize(s));
+    }
     float best = time_shape(best_shape);
     auto consider = [&](const LaunchShape &c) {
         const float med = time_shape(c);
