@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu((P == F16 && (LF & LF_PREFETCH) == 0) ? 6 : 1)))
 normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
                                                          int64_t stride, CgState *st, double *partials,
-                                                         int max_blocks, int nrhs, int ngroups, int tmap)
+                                                         int max_blocks, int nrhs, int ngroups, TileMap tmap)
 {
     typedef typename RealOf<P>::type T;
     int grp;
@@ -510,7 +510,7 @@ static void launch_normal_dot(const Gauge &gauge, const CgVectors &v, LaunchShap
     const int64_t stride = field_bytes(g, P, 1);
     const LinkRef L = gauge.ref(P, R);
     const int G = (v.nrhs + sh.rhs_per_thread - 1) / sh.rhs_per_thread;
-    const int tmap = tile_map(g, sh.block, sh.xcd_slab);
+    const TileMap tmap = tile_map(g, sh.block, sh.xcd_slab, time_run(g, sh.block, v.nrhs, P, sh.trun));
     const dim3 grid(tile_map_blocks(g, sh.block, tmap, G));
     const size_t lds = hop_lds_bytes(g, P, sh.rhs_per_thread, sh);
 #define LQS_ND(K, LF)                                                                                             \

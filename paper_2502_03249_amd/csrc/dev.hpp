@@ -515,6 +515,106 @@ template <> struct Roundtrip<F16> {
     }
 };
 
+// ---------------------------------------------------------------------------
+// FP16 storage: products on the stored binary16 pairs
+//
+// A stored complex binary16 number is one 32-bit word, real part in the low
+// half.  v_dot2_f32_f16 forms lo*lo + hi*hi + c; binary16 products are exact
+// in binary32, so the arithmetic is binary32 as in the decoded form, without
+// converting the operands first.  A complex product takes two dot2, the signs
+// and the order of the halves set by one bit operation on the vector word.
+typedef _Float16 hpair __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2(bitcast<hpair>(a), bitcast<hpair>(b), c, false);
+}
+// dot2(a, b, 0): the three-operand encoding with the constant 0, where the
+// compiler would pick the accumulating two-operand form and first move a
+// zero into the destination (one extra instruction per chain).
+__device__ __forceinline__ float dot2z(uint32_t a, uint32_t b)
+{
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ uint32_t swap_h(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
+constexpr uint32_t NEG_HI = 0x80000000u, NEG_LO = 0x00008000u, NEG_BOTH = 0x80008000u;
+__device__ __forceinline__ uint32_t pack_h(float re, float im)
+{
+    struct P { half_t lo, hi; } p = {to_half(re), to_half(im)};
+    return bitcast<uint32_t>(p);
+}
+
+// An SU(3) matrix as binary16 pair words e[row][col].
+struct M3H {
+    uint32_t e[3][3];
+};
+
+// conj(x y - z w) as a pair word: binary32 sums of the exact products, in a
+// fixed order, rounded to binary16.
+__device__ __forceinline__ uint32_t conj_cross_h(uint32_t x, uint32_t y, uint32_t z, uint32_t w)
+{
+    const float re = dot2(z, w ^ NEG_LO, dot2z(x, y ^ NEG_HI));              // xr yr - xi yi - zr wr + zi wi
+    const float nim = dot2(z, swap_h(w), dot2z(x ^ NEG_BOTH, swap_h(y)));  // -(xr yi + xi yr) + zr wi + zi wr
+    return pack_h(re, nim);
+}
+
+// The link words of LinkIO<F16, R>::Raw as a matrix; with 12 reals the third
+// row is rebuilt as conj(row0 x row1) and rounded to binary16 like a stored
+// row.
+template <int R, typename Raw> __device__ __forceinline__ M3H link_words(const Raw &r)
+{
+    M3H u;
+    u.e[0][0] = r.a.w[0];
+    u.e[0][1] = r.a.w[1];
+    u.e[0][2] = r.a.w[2];
+    u.e[1][0] = r.a.w[3];
+    if constexpr (R == 12) {
+        u.e[1][1] = r.c.w[0];
+        u.e[1][2] = r.c.w[1];
+        u.e[2][0] = conj_cross_h(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
+        u.e[2][1] = conj_cross_h(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
+        u.e[2][2] = conj_cross_h(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
+    } else {
+        u.e[1][1] = r.b.w[0];
+        u.e[1][2] = r.b.w[1];
+        u.e[2][0] = r.b.w[2];
+        u.e[2][1] = r.b.w[3];
+        u.e[2][2] = r.t;
+    }
+    return u;
+}
+
+// acc += f U v (FWD) or acc += f U^dag v, for the stored FP16 colour vector w
+// (three pair words and the site scale) and f = +-scale.  Component a sums its
+// three terms b = 0, 1, 2 in dot2 order, then one fused multiply-add by f.
+//   U v:      re = dot2(u_ab, (vr, -vi)),  im = dot2(u_ab, (vi, vr))
+//   U^dag v:  re = dot2(u_ba, (vr, vi)),   im = dot2(u_ba, (vi, -vr))
+template <bool FWD> __device__ __forceinline__ void accum_h(V3<float> &acc, const M3H &u, const W16 &w, bool negate)
+{
+    uint32_t x[3], y[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        x[b] = FWD ? (w.w[b] ^ NEG_HI) : w.w[b];
+        y[b] = FWD ? swap_h(w.w[b]) : (swap_h(w.w[b]) ^ NEG_HI);
+    }
+    const float sc = bitcast<float>(w.w[3]);
+    const float f = negate ? -sc : sc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t m0 = FWD ? u.e[a][0] : u.e[0][a];
+        float re = dot2z(m0, x[0]), im = dot2z(m0, y[0]);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            const uint32_t m = FWD ? u.e[a][b] : u.e[b][a];
+            re = dot2(m, x[b], re);
+            im = dot2(m, y[b], im);
+        }
+        acc.c[a].re = fused(f, re, acc.c[a].re);
+        acc.c[a].im = fused(f, im, acc.c[a].im);
+    }
+}
+
 // Convert a vector between real types.
 template <typename To, typename From> __device__ __forceinline__ V3<To> vcast(const V3<From> &v)
 {

@@ -15,7 +15,7 @@ namespace lqs {
 template <int P, int R, int K, bool DAG, int LF>
 __global__ void __launch_bounds__(512) hop_kernel(Geom g, LinkRef L, int parity, int nrhs, const char *in,
                                                   int64_t in_stride, char *out, int64_t out_stride,
-                                                  const CgState *gate, int gate_mode, int ngroups, int tmap)
+                                                  const CgState *gate, int gate_mode, int ngroups, TileMap tmap)
 {
     typedef typename RealOf<P>::type T;
     int grp;
@@ -58,7 +58,7 @@ static void launch_k(const Geom &g, LinkRef L, int dagger, int parity, int nrhs,
 {
     const int64_t stride = field_bytes(g, P, 1);
     const int G = (nrhs + K - 1) / K;
-    const int tmap = tile_map(g, sh.block, sh.xcd_slab);
+    const TileMap tmap = tile_map(g, sh.block, sh.xcd_slab, time_run(g, sh.block, nrhs, P, sh.trun));
     const dim3 grid(tile_map_blocks(g, sh.block, tmap, G));
     const size_t lds = hop_lds_bytes(g, P, K, sh);
     const int lf = (L.temporal ? LF_TEMPORAL : 0) | (sh.stream_links ? LF_STREAM : 0) | (lds ? LF_LDS : 0);
@@ -118,10 +118,14 @@ void launch_hop_gated(const Geom &g, LinkRef L, int prec, int recon, int dagger,
 
 // Default shapes from measured sweeps on 32^4, 32^3x8 and 64^3x16: from 4
 // vectors on, 4 right-hand sides per thread in 256-thread blocks with the
-// time-inner block -> tile map and prefetched words (steady state, 64^3x16,
-// 4 vectors: FP16 12-real 154 against 197 us without prefetch, FP32 250
-// against 331, FP64 12-real 501 against 623; 16 vectors 10-20 % faster on
-// 32^4 and 64^3x16); 2 per thread in 128-thread blocks for 2-3 vectors, also
+// pencil block -> tile map in runs of time slices (time_run) and prefetched
+// words (steady state, 64^3x16, 4 vectors: FP16 12-real 154 against 197 us
+// without prefetch, FP32 250 against 331, FP64 12-real 501 against 623; 16
+// vectors 10-20 % faster on 32^4 and 64^3x16; the pencil map against
+// time-inner over all slices: 32^4 FP16 12-real 4 vectors 33.7 against
+// 41.9 us, FP64 18-real 16 vectors 458 against 499, 64^3x16 FP64 18-real
+// 16 vectors 1739 against 1946, 32^3x8 FP32 12-real 16 vectors 38 against
+// 49, elsewhere within 3 %); 2 per thread in 128-thread blocks for 2-3 vectors, also
 // prefetched (3 vectors at 64^3x16: FP32 12-real 252 against 336 us, FP64
 // 18-real 688 against 903 us; 2 vectors 0-8 % faster).  Links are streamed
 // when their footprint exceeds STREAM_LINK_BYTES and one group of right-hand
@@ -137,7 +141,7 @@ LaunchShape default_hop_shape(const LinkRef &L, int nrhs)
     if (nrhs >= 4) {
         sh.block = 256;
         sh.rhs_per_thread = 4;
-        sh.xcd_slab = 2;
+        sh.xcd_slab = 3;
         sh.prefetch = 1;
     } else if (nrhs >= 2) {
         sh.block = 128;

@@ -178,10 +178,12 @@ struct LaunchShape {
     int block = 256;       // threads per block
     int rhs_per_thread = 1;
     int stream_links = 0;  // 1: link words fetched with streaming (nontemporal) loads
-    int xcd_slab = -1;     // block -> tile map: 0 round robin, 1 one slab per XCD, -1 by lattice shape
+    int xcd_slab = -1;     // block -> tile map: 0 round robin, 1 one slab per XCD, 2 time-inner,
+                           // 3 pencil, -1 by lattice shape
     int lds = 0;           // 1: x and y neighbours from an LDS window of the block's input sites
     int prefetch = 0;      // 1 (no LDS window): the words of a group of directions requested
                            // before their products (LF_PREFETCH)
+    int trun = -1;         // time-inner and pencil maps: time slices per run (0: all, -1: time_run)
 };
 // Link footprint from which the hop streams its links by default: beyond
 // about three quarters of the 256 MB last-level cache (MALL) the links of one

@@ -3,10 +3,11 @@
 // For a (device, kernel, lattice, precision, link format, nrhs) key the tuner
 // times every candidate shape (threads per block x right-hand sides per
 // thread x cached or streaming link loads x prefetched words, then the other
-// block -> XCD maps and LDS staging of the input window for the best of these)
+// block -> XCD maps, with runs of time slices, and LDS staging of the input
+// window for the best of these)
 // with HIP events on the caller's stream, keeps the one with the lowest
 // median time, and stores it in a flat JSON object
-// {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds,prefetch", ...} that
+// {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds,prefetch,trun", ...} that
 // later runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
 #include <algorithm>
@@ -46,17 +47,17 @@ Tuner::Tuner(const char *p)
 }
 
 // On a hit the stored fields replace those of `out`; an entry without the
-// third, fourth, fifth or sixth field keeps out.stream_links, out.xcd_slab,
-// out.lds or out.prefetch.
+// third to seventh field keeps out.stream_links, out.xcd_slab, out.lds,
+// out.prefetch or out.trun.
 bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) const
 {
     auto it = cache.find(key);
     if (it == cache.end()) return false;
-    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab, ld = out.lds, pf = out.prefetch;
-    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld, &pf);
+    int b = 0, k = 0, st = out.stream_links, sl = out.xcd_slab, ld = out.lds, pf = out.prefetch, tr = out.trun;
+    const int n = std::sscanf(it->second.c_str(), "%d,%d,%d,%d,%d,%d,%d", &b, &k, &st, &sl, &ld, &pf, &tr);
     if (n < 2) return false;
     if (b < 64 || b > max_block || (b & 63) || !(k == 1 || k == 2 || k == 4) || !(st == 0 || st == 1) ||
-        !(sl >= -1 && sl <= 2) || !(ld == 0 || ld == 1) || !(pf == 0 || pf == 1))
+        !(sl >= -1 && sl <= 3) || !(ld == 0 || ld == 1) || !(pf == 0 || pf == 1) || tr < -1)
         return false;
     out.block = b;
     out.rhs_per_thread = k;
@@ -64,6 +65,7 @@ bool Tuner::lookup(const std::string &key, LaunchShape &out, int max_block) cons
     out.xcd_slab = sl;
     out.lds = ld;
     out.prefetch = pf;
+    out.trun = tr;
     return true;
 }
 
@@ -71,7 +73,7 @@ void Tuner::store(const std::string &key, const LaunchShape &v)
 {
     cache[key] = std::to_string(v.block) + "," + std::to_string(v.rhs_per_thread) + "," +
                  std::to_string(v.stream_links) + "," + std::to_string(v.xcd_slab) + "," + std::to_string(v.lds) +
-                 "," + std::to_string(v.prefetch);
+                 "," + std::to_string(v.prefetch) + "," + std::to_string(v.trun);
 }
 
 void Tuner::save() const
@@ -216,10 +218,18 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     LaunchShape flip = best_shape;
     flip.xcd_slab = xcd_slab_auto(g, flip.block) ? 0 : 1;
     consider(flip);
-    // and the time-inner map, where whole tiles make up a time slice
-    LaunchShape tin = best_shape;
-    tin.xcd_slab = 2;
-    if (tile_map(g, tin.block, 2) < 0) consider(tin);
+    // and the time-inner and pencil maps, where whole tiles make up a time
+    // slice or a z plane, over all time slices and in runs of 8, 4 and 2
+    const LaunchShape base = best_shape;
+    for (int mode : {2, 3})
+        for (int run : {0, 8, 4, 2}) {
+            if (run >= g.n[3]) continue;
+            LaunchShape m = base;
+            m.xcd_slab = mode;
+            m.trun = run;
+            if (m.xcd_slab == base.xcd_slab && m.trun == base.trun) continue;
+            if (tile_map(g, m.block, mode, run).kind == (mode == 2 ? TM_TIME : TM_PENCIL)) consider(m);
+        }
     // then the kernel with its x/y neighbours staged through LDS, where the window fits
     LaunchShape staged = best_shape;
     staged.lds = 1;

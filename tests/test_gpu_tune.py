@@ -42,9 +42,9 @@ def test_tuning_cache_roundtrip_and_identical_results(tmp_path):
     assert any("|hop|8x8x8x16|p0|r18|n4" in k for k in keys)
     assert any("|normal_dot|8x8x8x16|p1|r18|n1" in k for k in keys)
     for v in entries.values():
-        blk, k, st, sl, ld, pf = (int(t) for t in v.split(","))
-        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1, 2)
-        assert ld in (0, 1) and pf in (0, 1) and (pf == 0 or ld == 0)
+        blk, k, st, sl, ld, pf, tr = (int(t) for t in v.split(","))
+        assert blk in (64, 128, 256, 512) and k in (1, 2, 4) and st in (0, 1) and sl in (-1, 0, 1, 2, 3)
+        assert ld in (0, 1) and pf in (0, 1) and (pf == 0 or ld == 0) and tr in (-1, 0, 2, 4, 8)
 
     # the persistent multi-lattice solve tunes its resident blocks per compute unit
     tuned = lqs.Context(0, tune_cache=cache, tuning=True)
@@ -433,3 +433,41 @@ def test_prefetch_multi_rhs_bit_identical(tmp_path, prec, recon, bound):
     if sols:
         for k in range(n):
             assert oracle.true_residual(dims, U, mass, b[k], sols[0][0][k]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,recon,bound", [(lqs.F64, 18, 1e-12), (lqs.F16, 12, 4e-3)])
+def test_tile_maps_and_time_runs_bit_identical(tmp_path, prec, recon, bound):
+    """Time-inner and pencil block -> tile maps, over all time slices and in runs of 2 and 4, on a
+    lattice whose z planes hold whole 256-site tiles: the hop of five vectors (4 per thread, 2
+    groups) and a one-vector solve give the round-robin map's bits and iteration counts."""
+    dims, mass, n = (32, 16, 4, 8), 0.05, 5
+    U = synth.gauge(dims, "smooth", seed=101, eps=0.3)
+    srcs = np.stack([synth.source(dims, 1, seed=1010 + k) for k in range(n)])
+    b = synth.source(dims, 0, seed=1020)
+    cache = str(tmp_path / "tune.json")
+    key = lambda kern, nn: "|".join([_arch(), kern, "32x16x4x8", "p%d" % prec, "r%d" % recon, "n%d" % nn])
+    maps = ["0,0", "2,0", "2,2", "3,0", "3,4", "3,2"]
+    outs, sols = [], []
+    for m in maps:
+        ents = {key("hop", n): "256,4,0,%s,0,1,%s" % tuple(m.split(",")),
+                key("hop", 1): "256,1,0,%s,0,0,%s" % tuple(m.split(",")),
+                key("normal_dot", 1): "256,1,0,%s,0,1,%s" % tuple(m.split(","))}
+        with open(cache, "w") as f:
+            json.dump(ents, f)
+        ctx = lqs.Context(0, tune_cache=cache)
+        g = gauge(ctx, dims, U)
+        outs.append(lex_of(ctx, lqs.dslash_apply(ctx, g, field(ctx, dims, srcs, 1, prec), recon=recon), squeeze=False))
+        bf = field(ctx, dims, b, 0)
+        xf = bf.like().zero_()
+        st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=1e-10, inner_prec=prec, inner_recon=recon,
+                          reliable_interval=100)
+        assert st[0]["status"] == 0
+        sols.append((lex_of(ctx, xf), st[0]["iters"]))
+        ctx.close()
+    for y in outs[1:]:
+        assert np.array_equal(y, outs[0])
+    for x, it in sols[1:]:
+        assert np.array_equal(x, sols[0][0]) and it == sols[0][1]
+    for k in range(n):
+        assert rel(outs[0][k], oracle.dslash(dims, U, srcs[k], 0)) <= bound
+    assert oracle.true_residual(dims, U, mass, b, sols[0][0]) <= 1e-10
