@@ -545,23 +545,30 @@ __device__ __forceinline__ uint32_t pack_h(float re, float im)
     return bitcast<uint32_t>(p);
 }
 
-// An SU(3) matrix as binary16 pair words e[row][col].
+// An SU(3) matrix as binary16 pair words e[row][col].  With 12 stored reals
+// the rebuilt third row is e[2][b] + lo[b]: its binary32 value rounded to
+// binary16 and the rounding remainder, again in binary16 (about 22 bits
+// together, where the third row alone in binary16 made some mixed solves
+// take 3-6 % more iterations).
 struct M3H {
     uint32_t e[3][3];
+    uint32_t lo[3];
 };
 
-// conj(x y - z w) as a pair word: binary32 sums of the exact products, in a
-// fixed order, rounded to binary16.
-__device__ __forceinline__ uint32_t conj_cross_h(uint32_t x, uint32_t y, uint32_t z, uint32_t w)
+// conj(x y - z w) from pair words: binary32 sums of the exact products, in a
+// fixed order, as binary16 pair words hi + lo.
+__device__ __forceinline__ void conj_cross_h(uint32_t x, uint32_t y, uint32_t z, uint32_t w, uint32_t &hi, uint32_t &lo)
 {
     const float re = dot2(z, w ^ NEG_LO, dot2z(x, y ^ NEG_HI));              // xr yr - xi yi - zr wr + zi wi
     const float nim = dot2(z, swap_h(w), dot2z(x ^ NEG_BOTH, swap_h(y)));  // -(xr yi + xi yr) + zr wi + zi wr
-    return pack_h(re, nim);
+    const hpair h = {(half_t)re, (half_t)nim};
+    const hpair l = {(half_t)(re - (float)h.x), (half_t)(nim - (float)h.y)};
+    hi = bitcast<uint32_t>(h);
+    lo = bitcast<uint32_t>(l);
 }
 
 // The link words of LinkIO<F16, R>::Raw as a matrix; with 12 reals the third
-// row is rebuilt as conj(row0 x row1) and rounded to binary16 like a stored
-// row.
+// row is rebuilt as conj(row0 x row1).
 template <int R, typename Raw> __device__ __forceinline__ M3H link_words(const Raw &r)
 {
     M3H u;
@@ -572,9 +579,9 @@ template <int R, typename Raw> __device__ __forceinline__ M3H link_words(const R
     if constexpr (R == 12) {
         u.e[1][1] = r.c.w[0];
         u.e[1][2] = r.c.w[1];
-        u.e[2][0] = conj_cross_h(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
-        u.e[2][1] = conj_cross_h(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
-        u.e[2][2] = conj_cross_h(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
+        conj_cross_h(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1], u.e[2][0], u.lo[0]);
+        conj_cross_h(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2], u.e[2][1], u.lo[1]);
+        conj_cross_h(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0], u.e[2][2], u.lo[2]);
     } else {
         u.e[1][1] = r.b.w[0];
         u.e[1][2] = r.b.w[1];
@@ -587,10 +594,12 @@ template <int R, typename Raw> __device__ __forceinline__ M3H link_words(const R
 
 // acc += f U v (FWD) or acc += f U^dag v, for the stored FP16 colour vector w
 // (three pair words and the site scale) and f = +-scale.  Component a sums its
-// three terms b = 0, 1, 2 in dot2 order, then one fused multiply-add by f.
+// three terms b = 0, 1, 2 in dot2 order (a third-row element of a 12-real
+// link as its hi part, then its lo part), then one fused multiply-add by f.
 //   U v:      re = dot2(u_ab, (vr, -vi)),  im = dot2(u_ab, (vi, vr))
 //   U^dag v:  re = dot2(u_ba, (vr, vi)),   im = dot2(u_ba, (vi, -vr))
-template <bool FWD> __device__ __forceinline__ void accum_h(V3<float> &acc, const M3H &u, const W16 &w, bool negate)
+template <bool FWD, int R>
+__device__ __forceinline__ void accum_h(V3<float> &acc, const M3H &u, const W16 &w, bool negate)
 {
     uint32_t x[3], y[3];
 #pragma unroll
@@ -604,11 +613,20 @@ template <bool FWD> __device__ __forceinline__ void accum_h(V3<float> &acc, cons
     for (int a = 0; a < 3; ++a) {
         const uint32_t m0 = FWD ? u.e[a][0] : u.e[0][a];
         float re = dot2z(m0, x[0]), im = dot2z(m0, y[0]);
+        if (R == 12 && FWD && a == 2) {
+            re = dot2(u.lo[0], x[0], re);
+            im = dot2(u.lo[0], y[0], im);
+        }
 #pragma unroll
         for (int b = 1; b < 3; ++b) {
             const uint32_t m = FWD ? u.e[a][b] : u.e[b][a];
             re = dot2(m, x[b], re);
             im = dot2(m, y[b], im);
+            if (R == 12 && (FWD ? a == 2 : b == 2)) {
+                const uint32_t l = u.lo[FWD ? b : a];
+                re = dot2(l, x[b], re);
+                im = dot2(l, y[b], im);
+            }
         }
         acc.c[a].re = fused(f, re, acc.c[a].re);
         acc.c[a].im = fused(f, im, acc.c[a].im);

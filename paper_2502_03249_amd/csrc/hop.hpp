@@ -251,8 +251,8 @@ __device__ __forceinline__ void hop_site_h(const Geom &g, const LinkRef &L, int 
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     if (!active[j]) continue;
-                    if ((d & 1) == 0) accum_h<true>(acc[j], u, vr[k][j], (s.negf >> mu) & 1);
-                    else accum_h<false>(acc[j], u, vr[k][j], !((s.negb >> mu) & 1));
+                    if ((d & 1) == 0) accum_h<true, R>(acc[j], u, vr[k][j], (s.negf >> mu) & 1);
+                    else accum_h<false, R>(acc[j], u, vr[k][j], !((s.negb >> mu) & 1));
                 }
             }
         }
@@ -271,7 +271,7 @@ __device__ __forceinline__ void hop_site_h(const Geom &g, const LinkRef &L, int 
             const int nbr = s.fwd[mu];
             const bool lw = (LF & LF_LDS) && mu < 2 && nbr >= w0 && nbr < w0 + wlen;
             const W16 v = lw ? SIO::load_raw(win + j * win_stride, wlen, nbr - w0) : SIO::load_raw(in + j * in_stride, g.vh, nbr);
-            accum_h<true>(acc[j], uf, v, nf);
+            accum_h<true, R>(acc[j], uf, v, nf);
         }
         const M3H ub =
             link_words<R>(LIO::load_raw(lb + (2 * mu + 1 - parity) * L.block_bytes, L.pitch, ub_unit ? g.vh : s.bwd[mu]));
@@ -281,7 +281,7 @@ __device__ __forceinline__ void hop_site_h(const Geom &g, const LinkRef &L, int 
             const int nbr = s.bwd[mu];
             const bool lw = (LF & LF_LDS) && mu < 2 && nbr >= w0 && nbr < w0 + wlen;
             const W16 v = lw ? SIO::load_raw(win + j * win_stride, wlen, nbr - w0) : SIO::load_raw(in + j * in_stride, g.vh, nbr);
-            accum_h<false>(acc[j], ub, v, nb);
+            accum_h<false, R>(acc[j], ub, v, nb);
         }
     }
 }
