@@ -5,8 +5,9 @@
 // thread x cached or streaming link loads x prefetched words, then the other
 // block -> XCD maps, with runs of time slices, and LDS staging of the input
 // window for the best of these)
-// with HIP events on the caller's stream, keeps the one with the lowest
-// median time, and stores it in a flat JSON object
+// with HIP events on the caller's stream (bursts of back-to-back launches),
+// keeps the one with the lowest median time if it beats the default again in
+// a second, alternating timing, and stores it in a flat JSON object
 // {"key": "block,rhs_per_thread,stream_links,xcd_slab,lds,prefetch,trun", ...} that
 // later runs load.  Tuning runs
 // write only into library scratch buffers, never into caller memory.
@@ -166,18 +167,25 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
         if (is_dot) launch_normal_dot_shape(gauge, v, c, s);
         else launch_hop_gated(g, L, prec, recon, 0, 1, nrhs, in, out, nullptr, 0, c, s);
     };
+    // Launches are timed in bursts of back to back calls, as a solver issues
+    // them: one launch between two events also counts its own start, which on
+    // lattices whose launches take 10-20 us had favoured shapes that are
+    // slower in a stream of launches.  The normal kernel only reads the state
+    // records (gate and mass), so they are set once.
+    constexpr int BURST = 4;
     auto time_shape = [&](const LaunchShape &c) {
+        if (is_dot) LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
+        launch_once(c);
+        launch_once(c);
         std::vector<float> t;
-        for (int rep = 0; rep < 7; ++rep) {
-            if (is_dot)
-                LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
+        for (int rep = 0; rep < 5; ++rep) {
             LQS_HIP(hipEventRecord(e0, s));
-            launch_once(c);
+            for (int k = 0; k < BURST; ++k) launch_once(c);
             LQS_HIP(hipEventRecord(e1, s));
             LQS_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             LQS_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep >= 2) t.push_back(ms);
+            t.push_back(ms / BURST);
         }
         std::sort(t.begin(), t.end());
         return t[t.size() / 2];
@@ -194,9 +202,8 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     // first (the normal kernel's gate is set to running for every launch).
     {
         const auto w0 = std::chrono::steady_clock::now();
+        if (is_dot) LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
         for (int i = 0; i < 500; ++i) {
-            if (is_dot)
-                LQS_HIP(hipMemcpyAsync(st, tmpl.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
             launch_once(best_shape);
             if ((i & 3) == 3) {
                 LQS_HIP(hipStreamSynchronize(s));
@@ -235,6 +242,22 @@ void autotune(Ctx &ctx, const Gauge &gauge, const char *kernel, int prec, int re
     staged.lds = 1;
     staged.prefetch = 0;
     if (hop_lds_bytes(g, prec, staged.rhs_per_thread, staged) > 0) consider(staged);
+    // Confirm a winner against the default with fresh timings, the two
+    // alternating: on lattices whose launches take 10-20 us one noisy median
+    // had picked shapes up to 34 % slower than the default.
+    const LaunchShape def = default_hop_shape(L, nrhs);
+    auto same = [](const LaunchShape &a, const LaunchShape &b) {
+        return a.block == b.block && a.rhs_per_thread == b.rhs_per_thread && a.stream_links == b.stream_links &&
+               a.xcd_slab == b.xcd_slab && a.lds == b.lds && a.prefetch == b.prefetch && a.trun == b.trun;
+    };
+    if (!same(best_shape, def)) {
+        float td = 0.f, tb = 0.f;
+        for (int k = 0; k < 3; ++k) {
+            td += time_shape(def);
+            tb += time_shape(best_shape);
+        }
+        if (!(tb < MARGIN * td)) best_shape = def;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx.tuner->store(key, best_shape);
