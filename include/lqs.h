@@ -110,8 +110,9 @@ void lqs_ctx_destroy(lqs_ctx *ctx);
 
 /* Autotuning of launch shapes: 1 = sweep on first use of a (kernel, lattice,
  * format, right-hand sides) key and cache the fastest (block size, sides per
- * thread, streaming link loads, block-to-XCD map, LDS staging of the input; a
- * shape must beat the built-in default by 2 %); 0 (default) = no sweeps:
+ * thread, streaming link loads, block-to-XCD map and its run of time slices,
+ * LDS staging of the input, prefetched loads; a shape must beat the built-in
+ * default by 2 %, twice); 0 (default) = no sweeps:
  * shapes already cached (loaded from tune_cache_path or tuned earlier in this
  * context) are used, the built-in defaults otherwise. */
 lqs_status lqs_set_tuning(lqs_ctx *ctx, int32_t enable);
