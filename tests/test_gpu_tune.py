@@ -435,17 +435,20 @@ def test_prefetch_multi_rhs_bit_identical(tmp_path, prec, recon, bound):
             assert oracle.true_residual(dims, U, mass, b[k], sols[0][0][k]) <= 1e-10
 
 
+@pytest.mark.parametrize("dims", [(32, 16, 4, 8), (32, 32, 4, 6)])
 @pytest.mark.parametrize("prec,recon,bound", [(lqs.F64, 18, 1e-12), (lqs.F16, 12, 4e-3)])
-def test_tile_maps_and_time_runs_bit_identical(tmp_path, prec, recon, bound):
-    """Time-inner and pencil block -> tile maps, over all time slices and in runs of 2 and 4, on a
-    lattice whose z planes hold whole 256-site tiles: the hop of five vectors (4 per thread, 2
-    groups) and a one-vector solve give the round-robin map's bits and iteration counts."""
-    dims, mass, n = (32, 16, 4, 8), 0.05, 5
+def test_tile_maps_and_time_runs_bit_identical(tmp_path, dims, prec, recon, bound):
+    """Time-inner and pencil block -> tile maps, over all time slices and in runs of 2 and 4, on
+    lattices whose z planes hold one or two whole 256-site tiles (32x32x4x6: two bands, and runs
+    of 4 over 6 slices end with a shorter run): the hop of five vectors (4 per thread, 2 groups)
+    and a one-vector solve give the round-robin map's bits and iteration counts."""
+    mass, n = 0.05, 5
+    tag = "x".join(str(d) for d in dims)
     U = synth.gauge(dims, "smooth", seed=101, eps=0.3)
     srcs = np.stack([synth.source(dims, 1, seed=1010 + k) for k in range(n)])
     b = synth.source(dims, 0, seed=1020)
     cache = str(tmp_path / "tune.json")
-    key = lambda kern, nn: "|".join([_arch(), kern, "32x16x4x8", "p%d" % prec, "r%d" % recon, "n%d" % nn])
+    key = lambda kern, nn: "|".join([_arch(), kern, tag, "p%d" % prec, "r%d" % recon, "n%d" % nn])
     maps = ["0,0", "2,0", "2,2", "3,0", "3,4", "3,2"]
     outs, sols = [], []
     for m in maps:
