@@ -52,16 +52,16 @@ struct TileMap {
     int p = 1;    // TM_PENCIL: tiles per z plane
     int run = 1;  // TM_TIME, TM_PENCIL: time slices per run (the last run may be shorter)
 };
-__device__ __forceinline__ int tile_group(int G, const TileMap &m, int nt, int &grp)
+__host__ __device__ __forceinline__ int tile_of_block(int b, int G, const TileMap &m, int nt, int &grp)
 {
-    const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+    const int xcd = b & 7, q = b >> 3;
     grp = q % G;
     const int qq = q / G;
     if (m.kind == TM_RR) return qq * 8 + xcd;
     if (m.kind == TM_SLAB) return xcd * m.n + qq;
     const int S = m.n, per = (S + 7) >> 3;  // tiles of one slice per XCD
     const int rb = qq / (per * m.run), r = qq - rb * per * m.run;
-    const int len = min(m.run, nt - rb * m.run);
+    const int len = m.run < nt - rb * m.run ? m.run : nt - rb * m.run;
     const int k = r / len, t = rb * m.run + (r - k * len);
     int s;
     if (m.kind == TM_TIME) {
@@ -71,6 +71,10 @@ __device__ __forceinline__ int tile_group(int G, const TileMap &m, int nt, int &
         s = o < S ? (o % nz) * m.p + o / nz : S;
     }
     return s < S ? t * S + s : -1;
+}
+__device__ __forceinline__ int tile_group(int G, const TileMap &m, int nt, int &grp)
+{
+    return tile_of_block(blockIdx.x, G, m, nt, grp);
 }
 
 // The round-robin map keeps the z and t neighbours of a tile on its XCD when
