@@ -5,12 +5,13 @@
 // Per iteration four kernels run back to back on one stream:
 //   1. t = D_oe p                                      (hop)
 //   2. q = m^2 p - D_eo t and <p,q>                     (hop + fused dot)
-//   3. x += alpha p, r -= alpha q and |r|^2             (fused update + norm)
-//   4. p = r + beta p
+//   3. r -= alpha q and |r|^2                           (fused update + norm)
+//   4. x += alpha p, p = r + beta p                     (one read of the old p)
 // The dot products are reduced in two fixed-order stages (wave shuffles and
 // LDS inside a block, then the last block to finish sums the block partials)
 // and alpha, beta stay on the device; the host only polls the state record.
 // Every few iterations a gated FP64 group runs between kernels 3 and 4:
+//   x += alpha p                                        (the step 4 owes)
 //   x += x_lo, x_lo = 0                                 (mixed precision)
 //   t64 = D_oe x, r_hi = b - (m^2 x - D_eo t64), |r_hi|^2, r = r_hi
 // It does nothing unless the state asks for it: after the iterated residual
@@ -201,8 +202,9 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
 }
 
 // ---------------------------------------------------------------------------
-// 3. alpha = rho / <p, q>; x_lo += alpha p, r -= alpha q, |r|^2
-//    (grid-stride, blockIdx.y = rhs)
+// 3. alpha = rho / <p, q>; r -= alpha q, |r|^2
+//    (grid-stride, blockIdx.y = rhs; x += alpha p is left to the p-update,
+//    which reads p anyway, or to the FP64 group's flush when that runs first)
 //
 // With nd_blocks > 0 every block sums the normal kernel's <p, q> partials
 // itself, in the same order, so all blocks hold the same alpha without a
@@ -216,27 +218,22 @@ normal_dot_kernel(Geom g, LinkRef L, const char *t, const char *p, char *q,
 // overlap with them (on small lattices that is its only site).
 
 template <int PA, int PI>
-__global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, char *r, const char *p, const char *q,
-                                                            int64_t sa, int64_t si, CgState *st,
-                                                            const double *pq_partials, int nd_blocks,
+__global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *r, const char *q, int64_t sa, int64_t si,
+                                                            CgState *st, const double *pq_partials, int nd_blocks,
                                                             double *partials, int max_blocks)
 {
     typedef typename RealOf<PA>::type T;
     const int rhs = blockIdx.y;
     CgState &S = st[rhs];
-    x += rhs * sa;
     r += rhs * sa;
-    p += rhs * si;
     q += rhs * si;
     const int stride = gridDim.x * blockDim.x;
     const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
     const int cf = c0 < vh ? c0 : vh - 1;  // a valid site for every thread (vh >= 1)
-    const typename SpinorIO<PI>::Raw praw = SpinorIO<PI>::load_raw(p, vh, cf), qraw = SpinorIO<PI>::load_raw(q, vh, cf);
-    const typename SpinorIO<PA>::Raw xraw = SpinorIO<PA>::load_raw(x, vh, cf), rraw = SpinorIO<PA>::load_raw(r, vh, cf);
+    const typename SpinorIO<PI>::Raw qraw = SpinorIO<PI>::load_raw(q, vh, cf);
+    const typename SpinorIO<PA>::Raw rraw = SpinorIO<PA>::load_raw(r, vh, cf);
     const int phase = S.phase;
-    issue_here(praw);
     issue_here(qraw);
-    issue_here(xraw);
     issue_here(rraw);
     if (phase != CG_RUNNING) return;
     double alpha_d = S.alpha;  // nd_blocks == 0: set by the FIN_DOT finalize
@@ -254,41 +251,50 @@ __global__ void __launch_bounds__(BLAS_BLOCK) update_kernel(int vh, char *x, cha
     }
     const T alpha = (T)alpha_d;
     double local = 0.0;
-    auto site = [&](int cb, const V3<T> &pv, const V3<T> &qv, V3<T> xv, V3<T> rv) {
+    auto site = [&](int cb, const V3<T> &qv, V3<T> rv) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            xv.c[a].re += alpha * pv.c[a].re;
-            xv.c[a].im += alpha * pv.c[a].im;
-            rv.c[a].re -= alpha * qv.c[a].re;
-            rv.c[a].im -= alpha * qv.c[a].im;
+            rv.c[a].re = fused(-alpha, qv.c[a].re, rv.c[a].re);
+            rv.c[a].im = fused(-alpha, qv.c[a].im, rv.c[a].im);
             local += (double)rv.c[a].re * (double)rv.c[a].re + (double)rv.c[a].im * (double)rv.c[a].im;
         }
-        SpinorIO<PA>::store(x, vh, cb, xv);
         SpinorIO<PA>::store(r, vh, cb, rv);
     };
-    if (c0 < vh)
-        site(c0, vcast<T>(SpinorIO<PI>::decode(praw)), vcast<T>(SpinorIO<PI>::decode(qraw)), SpinorIO<PA>::decode(xraw),
-             SpinorIO<PA>::decode(rraw));
+    if (c0 < vh) site(c0, vcast<T>(SpinorIO<PI>::decode(qraw)), SpinorIO<PA>::decode(rraw));
     for (int cb = c0 + stride; cb < vh; cb += stride)
-        site(cb, vcast<T>(SpinorIO<PI>::load(p, vh, cb)), vcast<T>(SpinorIO<PI>::load(q, vh, cb)),
-             SpinorIO<PA>::load(x, vh, cb), SpinorIO<PA>::load(r, vh, cb));
+        site(cb, vcast<T>(SpinorIO<PI>::load(q, vh, cb)), SpinorIO<PA>::load(r, vh, cb));
     const double s = block_sum(local);
     if (threadIdx.x == 0) partials[(int64_t)rhs * max_blocks + blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
-// 4. p = r + beta p
-
-// (as in the update kernel, the first site's operands are requested before
-// the gate)
+// 4. x += alpha p (x_lo in mixed precision), p = r + beta p
+//
+// The x update belongs to this iteration's alpha and the p before this
+// kernel; it is skipped when the FP64 group ran after the update kernel
+// (since_rel == 0: its flush already applied it).  No block writes the state.
+// (As in the update kernel, the first site's operands are requested before
+// the gate.)
 template <int PA, int PI>
-__global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char *r, char *p, int64_t sa, int64_t si,
-                                                             const CgState *st)
+__device__ __forceinline__ void x_step(V3<typename RealOf<PA>::type> &xv, const V3<typename RealOf<PA>::type> &pv,
+                                       typename RealOf<PA>::type alpha)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        xv.c[a].re = fused(alpha, pv.c[a].re, xv.c[a].re);
+        xv.c[a].im = fused(alpha, pv.c[a].im, xv.c[a].im);
+    }
+}
+
+template <int PA, int PI>
+__global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, char *x, const char *r, char *p, int64_t sa,
+                                                             int64_t si, const CgState *st)
 {
     typedef typename RealOf<PA>::type T;
     typedef typename RealOf<PI>::type TI;
     const int rhs = blockIdx.y;
     const CgState &S = st[rhs];
+    x += rhs * sa;
     r += rhs * sa;
     p += rhs * si;
     const int stride = gridDim.x * blockDim.x;
@@ -296,16 +302,46 @@ __global__ void __launch_bounds__(BLAS_BLOCK) pupdate_kernel(int vh, const char 
     const int cf = c0 < vh ? c0 : vh - 1;
     const typename SpinorIO<PA>::Raw rraw = SpinorIO<PA>::load_raw(r, vh, cf);
     const typename SpinorIO<PI>::Raw praw = SpinorIO<PI>::load_raw(p, vh, cf);
+    const typename SpinorIO<PA>::Raw xraw = SpinorIO<PA>::load_raw(x, vh, cf);
     const int phase = S.phase;
-    const T beta = (T)S.beta;
+    const bool xstep = S.since_rel != 0;
+    const T beta = (T)S.beta, alpha = (T)S.alpha;
     issue_here(rraw);
     issue_here(praw);
+    issue_here(xraw);
     if (phase != CG_RUNNING) return;
+    auto site = [&](int cb, const V3<T> &rv, const V3<T> &pv, V3<T> xv) {
+        if (xstep) {
+            x_step<PA, PI>(xv, pv, alpha);
+            SpinorIO<PA>::store(x, vh, cb, xv);
+        }
+        SpinorIO<PI>::store(p, vh, cb, vcast<TI>(direction_of<PA>(rv, pv, beta)));
+    };
     if (c0 < vh)
-        SpinorIO<PI>::store(
-            p, vh, c0, vcast<TI>(direction_of<PA>(SpinorIO<PA>::decode(rraw), vcast<T>(SpinorIO<PI>::decode(praw)), beta)));
+        site(c0, SpinorIO<PA>::decode(rraw), vcast<T>(SpinorIO<PI>::decode(praw)), SpinorIO<PA>::decode(xraw));
     for (int cb = c0 + stride; cb < vh; cb += stride)
-        SpinorIO<PI>::store(p, vh, cb, vcast<TI>(direction_at<PI, PA>(r, p, vh, cb, beta)));
+        site(cb, SpinorIO<PA>::load(r, vh, cb), vcast<T>(SpinorIO<PI>::load(p, vh, cb)),
+             xstep ? SpinorIO<PA>::load(x, vh, cb) : vzero<T>());
+}
+
+// FP64 group, first: x += alpha p for the iteration whose p-update has not
+// run yet (gate: reliable pending), with the p-update's arithmetic.
+template <int PA, int PI>
+__global__ void __launch_bounds__(BLAS_BLOCK) xflush_kernel(int vh, char *x, const char *p, int64_t sa, int64_t si,
+                                                            const CgState *st)
+{
+    typedef typename RealOf<PA>::type T;
+    const int rhs = blockIdx.y;
+    const CgState &S = st[rhs];
+    if (!S.reliable_pending) return;
+    const T alpha = (T)S.alpha;
+    x += rhs * sa;
+    p += rhs * si;
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < vh; cb += gridDim.x * blockDim.x) {
+        V3<T> xv = SpinorIO<PA>::load(x, vh, cb);
+        x_step<PA, PI>(xv, vcast<T>(SpinorIO<PI>::load(p, vh, cb)), alpha);
+        SpinorIO<PA>::store(x, vh, cb, xv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -489,8 +525,8 @@ void cg_fill_rates(lqs_cg_stats &o, const Gauge &gauge, int prec, int recon, int
     const double lps = gauge.temporal ? 6.0 + 2.0 / gauge.g.n[3] : 8.0;
     const double L = lps * real * recon / (nrhs > 0 ? nrhs : 1);
     const double sv = (double)spinor_bytes_per_site(prec), a = (double)spinor_bytes_per_site(prec == F64 ? F64 : F32);
-    // t = D_oe p; q = m^2 p - D_eo t; x, r updated from p, q; p = r + beta p
-    const double bytes = (L + 2 * sv) + (L + 3 * sv) + (4 * a + 2 * sv) + (a + 2 * sv);
+    // t = D_oe p; q = m^2 p - D_eo t; r updated from q; x and p updated from r and p
+    const double bytes = (L + 2 * sv) + (L + 3 * sv) + (2 * a + sv) + (3 * a + 2 * sv);
     const double n = (double)gauge.vh * o.iters;
     o.gflops = 1140.0 * n / t * 1e-9;
     o.gbytes_per_s = bytes * n / t * 1e-9;
@@ -559,7 +595,8 @@ void launch_normal_dot_shape(const Gauge &gauge, const CgVectors &v, LaunchShape
 
 // which 0: update (alpha from the nd_blocks <p,q> partials in v.partials, or
 // from the state when nd_blocks is 0; |r|^2 partials into v.partials2) and
-// its finalize; 1: p = r + beta p
+// its finalize; 1: x += alpha p (unless flushed), p = r + beta p; 2: the FP64
+// group's flush of x += alpha p
 template <int PA, int PI>
 static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, int nd_blocks, hipStream_t s)
 {
@@ -567,12 +604,14 @@ static void launch_blas(const Gauge &gauge, const CgVectors &v, int which, int n
     const int64_t sa = field_bytes(gauge.g, PA, 1), si = field_bytes(gauge.g, PI, 1);
     dim3 grid(blas_blocks(vh), v.nrhs);
     if (which == 0)
-        hipLaunchKernelGGL((update_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.xlo, (char *)v.r,
-                           (const char *)v.p, (const char *)v.q, sa, si, v.state, (const double *)v.partials,
-                           nd_blocks, v.partials2, v.max_blocks);
+        hipLaunchKernelGGL((update_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.r, (const char *)v.q,
+                           sa, si, v.state, (const double *)v.partials, nd_blocks, v.partials2, v.max_blocks);
+    else if (which == 1)
+        hipLaunchKernelGGL((pupdate_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.xlo,
+                           (const char *)v.r, (char *)v.p, sa, si, (const CgState *)v.state);
     else
-        hipLaunchKernelGGL((pupdate_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (const char *)v.r,
-                           (char *)v.p, sa, si, (const CgState *)v.state);
+        hipLaunchKernelGGL((xflush_kernel<PA, PI>), grid, dim3(BLAS_BLOCK), 0, s, vh, (char *)v.xlo,
+                           (const char *)v.p, sa, si, (const CgState *)v.state);
     LQS_HIP(hipGetLastError());
     if (which == 0) launch_finalize(v, v.partials2, grid.x, FIN_UPDATE, 0, 0, s);
 }
@@ -711,8 +750,13 @@ void cg_iteration(Ctx &ctx, const Gauge &gauge, CgVectors &v, hipStream_t s, boo
     if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 0, nd_blocks, s);
     else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 0, nd_blocks, s);
     else launch_blas<F32, F16>(gauge, v, 0, nd_blocks, s);
-    // FP64 residual group (gated)
-    if (with_reliable) cg_residual_group(ctx, gauge, v, 2, 0, s);
+    // FP64 residual group (gated), after the x step it needs
+    if (with_reliable) {
+        if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 2, 0, s);
+        else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 2, 0, s);
+        else launch_blas<F32, F16>(gauge, v, 2, 0, s);
+        cg_residual_group(ctx, gauge, v, 2, 0, s);
+    }
     // 4. p = r + beta p
     if (v.acc_prec == F64) launch_blas<F64, F64>(gauge, v, 1, 0, s);
     else if (v.prec == F32) launch_blas<F32, F32>(gauge, v, 1, 0, s);

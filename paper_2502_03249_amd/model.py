@@ -48,8 +48,9 @@ def cg_iteration_bytes(prec, acc_prec, recon=18, links_per_site=8):
     """Algorithmic HBM bytes per even site of one CG iteration (four kernels).
 
     hop t = D_oe p: links + p + t; hop q = m^2 p - D_eo t: links + t + p + q;
-    update: x, r read and written, p and q read; p = r + beta p: r, p read, p written.
+    update: r read and written, q read; x += alpha p and p = r + beta p: x read and
+    written, r and p read, p written.
     """
     L = links_per_site * link_bytes(prec, recon)
     s, a = spinor_bytes(prec), spinor_bytes(acc_prec)
-    return (L + 2 * s) + (L + 3 * s) + (4 * a + 2 * s) + (a + 2 * s)
+    return (L + 2 * s) + (L + 3 * s) + (2 * a + s) + (3 * a + 2 * s)
