@@ -107,8 +107,8 @@ __device__ void fin_residual(CgState &S, double r2, int mode)
 }
 
 // ---------------------------------------------------------------------------
-// The new search direction r + beta p at site cb, in the accumulation
-// precision (one fused multiply-add per component).
+// The new search direction r + beta p, in the accumulation precision (one
+// fused multiply-add per component).
 
 template <int PA>
 __device__ __forceinline__ V3<typename RealOf<PA>::type> direction_of(const V3<typename RealOf<PA>::type> &rv,
@@ -122,14 +122,6 @@ __device__ __forceinline__ V3<typename RealOf<PA>::type> direction_of(const V3<t
         o.c[a].im = fused(beta, pv.c[a].im, rv.c[a].im);
     }
     return o;
-}
-
-template <int P, int PA>
-__device__ __forceinline__ V3<typename RealOf<PA>::type> direction_at(const char *r, const char *p, int64_t vh, int cb,
-                                                                      typename RealOf<PA>::type beta)
-{
-    typedef typename RealOf<PA>::type TA;
-    return direction_of<PA>(SpinorIO<PA>::load(r, vh, cb), vcast<TA>(SpinorIO<P>::load(p, vh, cb)), beta);
 }
 
 // ---------------------------------------------------------------------------
