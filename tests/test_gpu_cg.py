@@ -111,6 +111,25 @@ def test_cg_warm_start_resume(ctx):
     assert oracle.true_residual(dims, U, mass, b, x) <= 1e-10
 
 
+@pytest.mark.parametrize("dims,mass,tol", [((4, 4, 4, 4), 0.1, 1e-13), ((8, 8, 8, 8), 0.05, 1e-12)])
+def test_cg_fp64_restart_near_rounding_limit(ctx, dims, mass, tol):
+    """An FP64 solve to a tolerance near the rounding limit: the iterated residual meets tol
+    before the true one does, so the FP64 check restarts CG from r = b - M x (beta = 0) at least
+    once.  That path applies the pending x step in the FP64 group before the check and skips it
+    in the p-update after; the solution must still meet tol by the oracle's residual, and the
+    GPU's own FP64 residual must agree with it."""
+    U = synth.gauge(dims, "haar", seed=61)
+    b = synth.source(dims, 0, seed=62)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xf = bf.like().zero_()
+    st = lqs.cg_solve(ctx, [(g, mass, bf, xf)], tol=tol, max_iter=20000)[0]
+    assert st["status"] == 0 and st["restarts"] >= 1, st
+    tr = oracle.true_residual(dims, U, mass, b, lex_of(ctx, xf))
+    assert tr <= tol
+    assert abs(tr - st["true_rel_residual"]) <= 0.05 * tr
+
+
 def test_cg_max_iter_reports_not_converged(ctx):
     dims, mass = (4, 4, 4, 4), 0.1
     U = synth.gauge(dims, "haar", seed=1000)
