@@ -82,3 +82,34 @@ def test_multishift_mixed_precision(ctx, prec, recon):
         xv = lex_of(ctx, x)
         assert oracle.true_residual(dims, U, m, b, xv) <= 1e-10
         assert abs(oracle.true_residual(dims, U, m, b, xv) - s["true_rel_residual"]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,recon", [(lqs.F64, 18), (lqs.F32, 12)])
+def test_multishift_seventeen_masses_with_a_repeated_base(ctx, prec, recon):
+    """The largest mass count (17: the base and 16 shifts, so the refinement runs as a block of
+    16 columns and a block of one), with the smallest mass given twice: the repeated mass is a
+    shift of zero, whose recurrence is the base's own.  Every mass meets tol by the oracle's
+    residual and its solution agrees with the oracle's within the condition bound; the two
+    copies of the base mass agree with each other (to rounding in FP64).  An 18th mass is rejected."""
+    dims = (4, 6, 8, 10)  # 960 sites per parity: ragged 256-site tiles
+    masses = [0.3, 0.3] + [0.35 + 0.1 * k for k in range(15)]
+    assert len(masses) == 17
+    U = synth.gauge(dims, "haar", seed=105)
+    b = synth.source(dims, 0, seed=106)
+    g = gauge(ctx, dims, U)
+    bf = field(ctx, dims, b, 0)
+    xs = [bf.like() for _ in masses]
+    st = lqs.cg_solve_multishift(ctx, g, masses, bf, xs, tol=1e-10, inner_prec=prec, inner_recon=recon)
+    sols = []
+    for m, x, s in zip(masses, xs, st):
+        assert s["status"] == 0, (m, s)
+        xv = lex_of(ctx, x)
+        assert oracle.true_residual(dims, U, m, b, xv) <= 1e-10, m
+        xo, _, _, _ = oracle.cg(dims, U, m, b, tol=1e-11)
+        assert rel(xv, xo) <= (m ** 2 + 64) / m ** 2 * 1e-10, m
+        sols.append(xv)
+    # FP64: the zero shift repeats the base's arithmetic; mixed: each copy is within the bound
+    kappa = (masses[0] ** 2 + 64) / masses[0] ** 2
+    assert rel(sols[1], sols[0]) <= (1e-12 if prec == lqs.F64 else 2 * kappa * 1e-10)
+    with pytest.raises(lqs.LqsError):
+        lqs.cg_solve_multishift(ctx, g, masses + [2.0], bf, xs + [bf.like()], tol=1e-10)
