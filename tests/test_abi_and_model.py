@@ -51,6 +51,8 @@ def test_field_bytes_and_validation(L):
     assert f(dims, 2, 3, ctypes.byref(n)) == 0 and n.value == 16 * 960 * 3
     assert f((ctypes.c_int32 * 4)(4, 5, 8, 10), 0, 1, ctypes.byref(n)) == -1
     assert f(dims, 0, 17, ctypes.byref(n)) == -1
+    assert f(dims, 0, 0, ctypes.byref(n)) == -1
+    assert f(dims, 2, 16, ctypes.byref(n)) == 0 and n.value == 16 * 960 * 16
     assert f(dims, 3, 1, ctypes.byref(n)) == -1
     L.lqs_strerror.restype = ctypes.c_char_p
     assert L.lqs_strerror(-4).decode().startswith("CG breakdown")

@@ -65,6 +65,11 @@ def test_cg_parameter_checks(setup):
     assert _status(lambda: lqs.cg_solve(ctx, [(g, -1.0, b, x)])) == lqs.EINVAL
     assert _status(lambda: lqs.cg_solve(ctx, [(g64, 0.1, b, x)], inner_prec=lqs.F16)) == lqs.EUNSUPPORTED
     assert _status(lambda: lqs.fermion_force(ctx, g, b, None, 1.0, mode=3)) == lqs.EINVAL
+    # an empty batch: no problem to solve is an argument error, not a silent success
+    L = lqs.lib()
+    prm = lqs.LqsCgParams(1e-10, 100, lqs.F64, 18, 0, 0.0, 0, 0)
+    stats = (lqs.LqsCgStats * 1)()
+    assert L.cg_solve(ctx.handle, 0, None, ctypes.byref(prm), stats, None) == lqs.EINVAL
 
 
 def test_nonfinite_source_reported(setup):
